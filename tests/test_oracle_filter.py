@@ -1,0 +1,203 @@
+"""Pins of the oracle's filter steps (Fig. 1: update, estimation, resampling,
+prediction) and of the whole SMC (CPU only): invariants, exact integer
+properties of systematic resampling, Box-Muller statistics, brute force over
+a small transform grid and recovery of known synthetic transforms."""
+
+import itertools
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import synth
+
+
+def _params(**kw):
+    lim = kw.pop("limit", list(np.deg2rad([15.0] * 3)) + [8.0] * 3)
+    p = dict(n_particles=64, n_iters=5, seed=7, score="dice", limit=lim, sigma_score=0.02,
+             sigma0=list(0.15 * np.asarray(lim)), anneal=0.85)
+    p.update(kw)
+    return p
+
+
+def geodesic_deg(p, q, orc):
+    R1, R2 = orc.euler_R(p[:3]), orc.euler_R(q[:3])
+    return float(np.degrees(np.arccos(np.clip((np.trace(R1.T @ R2) - 1) / 2, -1, 1))))
+
+
+# ------------------------------------------------------------------ update / normalise
+
+def test_loglik_shape(orc):
+    assert orc.loglik(1.0, "dice", 0.02) == 0.0
+    assert orc.loglik(0.0, "ssd", 0.1) == 0.0
+    assert orc.loglik(-np.inf, "ncc", 0.02) == -np.inf
+    zs = np.linspace(0, 1, 11)
+    ll = [orc.loglik(z, "ncc", 0.05) for z in zs]
+    assert np.all(np.diff(ll) > 0)
+    # a Gaussian in the deficit: doubling the deficit quadruples the log-likelihood
+    assert abs(orc.loglik(0.8, "dice", 0.05) / orc.loglik(0.9, "dice", 0.05) - 4.0) < 1e-12
+
+
+def test_normalise_invariants(orc):
+    rng = np.random.default_rng(0)
+    lw = rng.normal(-50, 10, 300)
+    x = rng.normal(size=(300, 6))
+    a = orc.normalise(lw, x)
+    assert a["w"].max() == 1.0 and not a["degenerate"]
+    wn = a["w"] / a["w"].sum()
+    assert abs(wn.sum() - 1.0) < 1e-15
+    assert np.allclose(a["est"], np.average(x, axis=0, weights=a["w"]), rtol=0, atol=1e-13)
+    assert abs(a["ess"] - 1.0 / np.sum(wn * wn)) < 1e-10
+    b = orc.normalise(lw + 123.25, x)  # shift invariance
+    assert np.allclose(b["w"], a["w"], rtol=1e-13, atol=0) and np.allclose(b["est"], a["est"], atol=1e-13)
+    eq = orc.normalise(np.zeros(50), x[:50])
+    assert abs(eq["ess"] - 50) < 1e-12
+    one = np.full(50, -np.inf)
+    one[17] = -3.0
+    o = orc.normalise(one, x[:50])
+    assert o["ess"] == 1.0 and np.array_equal(o["est"], x[17])
+    d = orc.normalise(np.full(10, -np.inf), x[:10])
+    assert d["degenerate"] and np.allclose(d["est"], x[:10].mean(0), atol=1e-15)
+
+
+# ------------------------------------------------------------------ resampling
+
+def _resample_bigint(w, u32):
+    n = len(w)
+    q = [int(np.floor(v * 2.0 ** 48)) for v in w]
+    Q = sum(q)
+    C = list(itertools.accumulate(q))
+    out = []
+    for j in range(n):
+        pointer = (Fraction(j) + Fraction(u32, 2 ** 32)) * Fraction(Q, n)
+        out.append(next(i for i, c in enumerate(C) if c > pointer))
+    return out, q, Q
+
+
+def test_systematic_resampling_exact(orc):
+    rng = np.random.default_rng(1)
+    for n in (1, 2, 7, 64, 257):
+        for _ in range(5):
+            w = np.exp(rng.normal(0, 3, n))
+            w /= w.max()
+            w[rng.random(n) < 0.2] = 0.0
+            w[int(rng.integers(n))] = 1.0
+            u = int(rng.integers(0, 2 ** 32))
+            anc = orc.resample(w, u)
+            ref, q, Q = _resample_bigint(w, u)
+            assert list(anc) == ref
+            counts = np.bincount(anc, minlength=n)
+            assert counts.sum() == n and np.all(np.diff(anc) >= 0)
+            for i in range(n):
+                lo = (n * q[i]) // Q
+                assert counts[i] in (lo, lo + 1) if (n * q[i]) % Q else counts[i] == lo
+
+
+def test_equal_weights_resample_to_identity(orc):
+    for u in (0, 1, 2 ** 31, 2 ** 32 - 1):
+        assert np.array_equal(orc.resample(np.ones(33), u), np.arange(33))
+
+
+# ------------------------------------------------------------------ random draws
+
+def test_box_muller_normals(orc):
+    g = np.array([orc.gauss6(11, 0, j, 3) for j in range(20000)])
+    assert np.all(np.abs(g.mean(0)) < 0.03) and np.all(np.abs(g.var(0) - 1) < 0.04)
+    assert stats.kstest(g.ravel(), "norm").pvalue > 0.01
+    c = np.corrcoef(g.T)
+    assert np.max(np.abs(c - np.eye(6))) < 0.03
+    assert not np.array_equal(orc.gauss6(11, 0, 5, 3), orc.gauss6(11, 1, 5, 3))  # pair id in counter
+    assert not np.array_equal(orc.gauss6(11, 0, 5, 3), orc.gauss6(11, 0, 5, 4))  # iteration in counter
+
+
+def test_init_uniform_in_limits(orc):
+    p = _params(n_particles=20000, x0=[0.1, -0.1, 0.0, 1.0, 2.0, -3.0])
+    x = orc.init_particles(p)
+    lo = np.asarray(p["x0"]) - np.asarray(p["limit"])
+    u = (x - lo) / (2 * np.asarray(p["limit"]))
+    assert np.all((u > 0) & (u <= 1))
+    for d in range(6):
+        assert stats.kstest(u[:, d], "uniform").pvalue > 0.01
+
+
+def test_perturb_reflects_and_anneals(orc):
+    p = _params(n_particles=4000, sigma0=[0.0] * 6)
+    x = orc.init_particles(p)
+    anc = np.arange(4000, dtype=np.int32)[::-1].copy()
+    assert np.array_equal(orc.perturb(p, 2, x, anc), x[anc])
+    p = _params(n_particles=4000)
+    xm = np.tile(np.asarray(p.get("x0", [0] * 6), float), (4000, 1))
+    k = 3
+    d = orc.perturb(p, k, xm, np.zeros(4000, np.int32)) - xm
+    sig = np.asarray(p["sigma0"]) * p["anneal"] ** (k - 1)
+    assert np.allclose(d.std(0) / sig, 1.0, atol=0.05)
+    big = _params(n_particles=4000, sigma0=[1.0] * 3 + [30.0] * 3)
+    y = orc.perturb(big, 1, xm, np.zeros(4000, np.int32))
+    assert np.all(np.abs(y) <= np.asarray(big["limit"]) + 1e-12)
+
+
+def test_last_iteration_does_not_resample(orc):
+    p = _params(n_particles=16, n_iters=3)
+    x = orc.init_particles(p)
+    z = np.linspace(0.1, 0.9, 16)
+    r = orc.filter_update(p, 3, x, z)
+    assert np.all(r["anc"] == -1)
+    r = orc.filter_update(p, 2, x, z)
+    assert np.all(r["anc"] >= 0)
+
+
+# ------------------------------------------------------------------ whole SMC
+
+def test_smc_deterministic(orc):
+    pair = synth.shell_pair(seed=2, side=32)
+    p = _params(n_particles=64, n_iters=4, limit=list(np.deg2rad([15.0] * 3)) + [4.0] * 3)
+    a = orc.smc_run(pair["src"], pair["tgt"], p)
+    b = orc.smc_run(pair["src"], pair["tgt"], p)
+    assert np.array_equal(a["est"], b["est"]) and np.array_equal(a["states"], b["states"])
+    assert np.array_equal(a["trace_score"], b["trace_score"])
+
+
+def test_smc_brute_force_grid(orc):
+    """Small exhaustive search: 24^3 filled ellipsoid (semi-axes 10/7/4.5), grid
+    {-10,-5,0,5,10} deg x {-2..2} voxels (5^6 points).  The brute-force argmax sits at the truth and the SMC
+    estimate lies within one grid step of it."""
+    ang = np.deg2rad([-10, -5, 0, 5, 10])
+    tr = np.arange(-2, 3, dtype=float)
+    gt = np.array([np.deg2rad(5), np.deg2rad(-5), 0.0, 1.0, -1.0, 2.0])
+    pair = synth.mask_pair((24, 24, 24), outer=(10.0, 7.0, 4.5), inner=None, gt=gt)
+    grid = np.array(list(itertools.product(ang, ang, ang, tr, tr, tr)))
+    pb = orc.Problem(pair["src"], pair["tgt"])
+    lim = list(np.deg2rad([12.5] * 3)) + [2.5] * 3
+    p = _params(limit=lim)
+    z = pb.score(p, grid)
+    best = grid[np.argmax(z)]
+    assert np.allclose(best, gt) and np.sum(z == z.max()) == 1
+    r = orc.smc_run(pair["src"], pair["tgt"], _params(limit=lim, n_particles=256, n_iters=12))
+    est = r["est"]
+    assert np.all(np.abs(est[:3] - best[:3]) <= np.deg2rad(5)) and np.all(np.abs(est[3:] - best[3:]) <= 1.0)
+
+
+def test_smc_recovers_mask_transforms(orc):
+    errs = []
+    for seed in range(1, 6):
+        pair = synth.mask_pair((64, 64, 64), outer=(24, 16, 10), inner=None, seed=seed)
+        r = orc.smc_run(pair["src"], pair["tgt"], _params(n_particles=256, n_iters=15, seed=seed,
+                                                             sigma_score=0.01))
+        errs.append((geodesic_deg(r["est"], pair["gt"], orc), np.linalg.norm(r["est"][3:] - pair["gt"][3:])))
+        assert r["trace_score"][-1] > r["trace_score"][0]
+    errs = np.array(errs)
+    assert np.median(errs[:, 0]) <= 1.0 and np.median(errs[:, 1]) <= 1.0, errs
+
+
+def test_smc_recovers_image_transform_ncc(orc):
+    errs = []
+    for seed in (1, 2):
+        pair = synth.speckle_pair(side=48, seed=seed, trans=12 * 48 / 160)
+        src = orc.Volume(pair["src"], fov=pair["src_fov"])
+        lim = list(np.deg2rad([20.0] * 3)) + [12 * 48 / 160] * 3
+        r = orc.smc_run(src, pair["tgt"], _params(n_particles=384, n_iters=15, seed=seed, score="ncc",
+                                                   limit=lim))
+        errs.append((geodesic_deg(r["est"], pair["gt"], orc), np.linalg.norm(r["est"][3:] - pair["gt"][3:])))
+    errs = np.array(errs)
+    assert np.max(errs[:, 0]) <= 1.0 and np.max(errs[:, 1]) <= 1.0, errs
