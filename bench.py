@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the registration hot path on one MI355X.
+
+A step is one whole registration of the 160^3 speckle workload: prior draw,
+K = 30 filter iterations over N = 2048 particles (warp-and-score of every
+particle over the whole target grid, update, normalise / estimate,
+systematic resampling, prediction), reading the estimate, and applying it to
+the source with warp_apply.  Inputs are resident in HBM before timing starts.
+
+value = N x V x K x steps / wall time (particle x voxel evaluations per
+second, V the nominal target grid).  The JSON line also carries the roofline
+of the dominant kernel (warp-and-score, timed live with HIP events on the
+library's stream) and the CPU oracle timed on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+# algorithmic work of one trilinear particle x voxel evaluation:
+# 8 source taps + the target byte shared by the 8 particles of a workgroup
+BYTES_PER_EVAL = 8.0 + 1.0 / 8.0
+# FP32 flops: 3 coordinate FMAs (6), 3 fraction subtractions (3), 7 lerps of a
+# subtraction and an FMA (21), fixed-point scale and round (2)
+FLOPS_PER_EVAL = 32.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pair, prm, target_s: float):
+    """The oracle's recipe-mode warp-and-score (>= 99 % of the path's work),
+    timed on a bounded sample of the prior particles on the host's cores."""
+    import numpy as np
+
+    import oracle
+
+    s = oracle.Volume(pair["src"], fov=pair["src_fov"])
+    t = oracle.Volume(pair["tgt"])
+    pb = oracle.Problem(s, t)
+    x = oracle.init_particles(prm)
+    V = pair["tgt"].size
+    threads = oracle.num_threads()
+    n = max(1, threads)
+    t0 = time.perf_counter()
+    pb.score(prm, x[:n])
+    dt = time.perf_counter() - t0
+    n2 = int(min(len(x), max(n, n * target_s / max(dt, 1e-3))))
+    n2 = max(threads, (n2 // threads) * threads)
+    t0 = time.perf_counter()
+    pb.score(prm, x[:n2])
+    dt = time.perf_counter() - t0
+    return dict(value=n2 * V / dt, unit="evals/s", cores=threads, kind="oracle",
+                sample=f"{n2} prior particles x {V} target voxels, one trilinear NCC evaluation each "
+                       f"({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--score", default="ncc", choices=["ncc", "ssd"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the registration path "
+              f"runs on a single MI355X, see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2504_19930_amd import binding, config
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    binding.lib()
+    torch.cuda.set_device(0)
+
+    log("generating the 160^3 speckle pair ...")
+    pair = synth.speckle_pair(side=160, seed=2)
+    prm = config.workload_params("speckle160")
+    prm["score"] = args.score
+    prm["sigma_score"] = config.SIGMA_SCORE[args.score]
+    N, K = prm["n_particles"], prm["n_iters"]
+    V = pair["tgt"].size
+
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    src, tgt, fov = dev(pair["src"]), dev(pair["tgt"]), dev(pair["src_fov"])
+    out = torch.zeros_like(tgt)
+    stream = torch.cuda.current_stream()
+    reg = binding.Registration(src, tgt, prm, src_fov=fov)
+    src_vol = binding.volume(src)
+
+    def step(s):
+        reg.reset(1000 + s)
+        reg.step(K)
+        est = reg.estimate()
+        binding.warp_apply(src_vol, est["matrix"], "trilinear", out)
+        return est
+
+    for w in range(args.warmup):
+        step(w)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps ...")
+    reg.profile(True)
+    reg.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        est = step(args.warmup + s)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = reg.profile_read()
+    reg.profile(False)
+
+    wall = t1 - t0
+    evals = float(N) * V * K * args.steps
+    value = evals / wall
+    score_launch_ms = prof["score_ms"] / max(1, prof["score_launches"])
+    evals_per_launch = float(N + 1) * V
+    achieved_tflops = evals_per_launch * FLOPS_PER_EVAL / (score_launch_ms * 1e-3) / 1e12
+    achieved_gbs = evals_per_launch * BYTES_PER_EVAL / (score_launch_ms * 1e-3) / 1e9
+    line = {
+        "metric": "particle×voxel evals/s",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"speckle160: 160^3 u8 speckle images, 60 deg apical-cone source FOV, "
+                               f"N={N} particles, K={K} iterations, {args.score.upper()}, trilinear; "
+                               f"one step = one full registration + warp_apply",
+                   "particles": N, "iterations": K, "target_voxels": V, "score": args.score},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_score_image (warp-and-score, trilinear)",
+                     "kernel_ms_per_launch": score_launch_ms, "launches": prof["score_launches"],
+                     "gather_GBs": achieved_gbs,
+                     "filter_ms_per_launch": prof["filter_ms"] / max(1, prof["filter_launches"])},
+        "final_score": est["score"],
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        cb = cpu_baseline(pair, prm, args.cpu_seconds)
+        line["cpu_baseline"] = cb
+        line["gpu_over_cpu"] = value / cb["value"]
+    reg.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,167 @@
+/*
+ * smc.h -- C ABI of the MI355X (gfx950) particle-filter rigid registration
+ * library, after Uruththirakodeeswaran et al., "Accelerated 3D-3D rigid
+ * registration of echocardiographic images obtained from apical window using
+ * particle filter" (arXiv 2504.19930).
+ *
+ * The problem (Abstract; Methods, Registration, Eq. 1): given a source and a
+ * target volume -- echo intensities or binary LV masks -- and an initial
+ * approximation of the rotation and translation limits, estimate the rigid
+ * transform (rx, ry, rz, tx, ty, tz) of Implementation Details (Euler 3D
+ * transform, homogeneous matrix of Eq. 3) that best aligns the warped source
+ * with the target, then apply it to every frame of the sequence.
+ *
+ * Conventions shared by every call:
+ *  - Volumes are uint8, x fastest (index i + nx (j + ny k)), voxel (i,j,k) at
+ *    s * (i,j,k) mm.  Volume and output pointers are DEVICE pointers owned by
+ *    the caller; they must stay valid while work queued on the stream runs.
+ *  - Angles are radians, translations mm.  The transform maps a target point p
+ *    to the source point q = R (p - c) + c + t with R = Rz(rz) Rx(rx) Ry(ry)
+ *    and c the target centre, (0.5 s_d)(n_d - 1).
+ *  - Every call returns smc_status; none throws.  A failure leaves a message
+ *    for smc_last_error() (thread-local).  Arguments are checked on the host
+ *    before anything is launched.  Errors on a context are sticky: once a
+ *    call on it fails, later calls on it return the same status.
+ *  - Calls are asynchronous on the caller's HIP stream unless marked "syncs".
+ */
+#ifndef SMC_H
+#define SMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SMC_OK = 0,
+    SMC_EINVAL = -1,   /* bad argument (null pointer, size, NaN, unsupported combination) */
+    SMC_ENOMEM = -2,   /* device allocation failed */
+    SMC_EDEVICE = -3,  /* a HIP call or kernel launch failed */
+    SMC_ESTATE = -4    /* call not valid in the context's current state */
+} smc_status;
+
+/* Similarity used as the filter's measurement (Fig. 1 caption).
+ * DICE: Eq. 4 on binary masks, over the whole target FOV, nearest neighbour.
+ * NCC:  Eq. 2 (squared correlation, 0..1) over the overlap.
+ * SSD:  mean squared difference of the mean-0 / std-1 normalised images
+ *       (Implementation Details) over the overlap; the score is its negative. */
+typedef enum { SMC_SCORE_DICE = 0, SMC_SCORE_NCC = 1, SMC_SCORE_SSD = 2 } smc_score;
+
+/* Sampling of the source at non-grid positions (Implementation Details:
+ * trilinear interpolation).  DICE requires NEAREST. */
+typedef enum { SMC_INTERP_NEAREST = 0, SMC_INTERP_TRILINEAR = 1 } smc_interp;
+
+typedef struct {
+    int32_t nx, ny, nz;      /* voxels, each >= 1 */
+    double sx, sy, sz;       /* spacing in mm, > 0 */
+    const uint8_t *data;     /* device, nz*ny*nx bytes */
+    const uint8_t *fov;      /* device or NULL; nonzero = inside the imaged field of view */
+} smc_volume;
+
+/* Filter parameters.  The paper defers them to its earlier work; the values
+ * used here are documented readings (rotation / translation limits from the
+ * Abstract, the rest tuned on synthetic data). */
+typedef struct {
+    uint32_t n_particles;    /* N, 1 .. 65536 */
+    uint32_t n_iters;        /* K >= 1: K evaluations, K-1 resample + predict steps */
+    uint64_t seed;           /* Philox4x32-10 key */
+    uint32_t pair_id;        /* third Philox counter word; distinguishes pairs of a batch */
+    int32_t score;           /* smc_score */
+    int32_t interp;          /* smc_interp */
+    double x0[6];            /* centre of the prior box */
+    double limit[6];         /* half-widths of the prior box, > 0 (rotation / translation limits) */
+    double sigma_score;      /* likelihood width: log w = -(z_max - z)^2 / (2 sigma^2) */
+    double sigma0[6];        /* random-walk width of the first prediction, >= 0 */
+    double anneal;           /* width factor per iteration, 0 < anneal <= 1 */
+    double min_overlap_frac; /* NCC / SSD: overlaps under this fraction of the target FOV get weight 0 */
+} smc_params;
+
+typedef struct smc_ctx smc_ctx;
+
+/* Fig. 1 (initialisation): validate the inputs, allocate the particle set and
+ * workspaces on the current device, prepare the source / target layouts and
+ * per-volume statistics, and draw the prior particle set uniformly in
+ * x0 +- limit.  src_fov / tgt_fov may be given inside the volumes.  Syncs once
+ * (to read the volume statistics).  *out owns its device memory until
+ * smc_destroy.  hip_stream is a hipStream_t (NULL = default stream). */
+smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt, const smc_params *p,
+                    void *hip_stream);
+
+/* Draw a fresh prior particle set with a new seed and rewind to iteration 0. */
+smc_status smc_reset(smc_ctx *ctx, uint64_t seed);
+
+/* Run n_iters iterations of Fig. 1 (evaluate -> update weights -> normalise
+ * and estimate -> resample -> predict); the last of the K iterations does not
+ * resample.  Fails with SMC_ESTATE past K. */
+smc_status smc_step(smc_ctx *ctx, uint32_t n_iters);
+
+/* The estimate after the last completed iteration: parameters, the 3x4
+ * target-mm -> source-mm matrix (row-major, Eq. 3 without its last row), the
+ * estimate's own score and the effective sample size.  Any output may be
+ * NULL.  Syncs. */
+smc_status smc_estimate(smc_ctx *ctx, double params[6], double mat3x4[12], double *score, double *ess);
+
+/* Host copies of the current particle set (N x 6), the log-weights of the
+ * last evaluation (N) and the last ancestors (N; -1 before any resampling).
+ * Any output may be NULL.  Syncs. */
+smc_status smc_get_particles(smc_ctx *ctx, double *states_n6, double *logw_n, int32_t *ancestors_n);
+
+/* Per-iteration trace (Fig. 5): score of the estimate before iteration 1 and
+ * after each iteration (K + 1 values), ESS per iteration (K) and the estimate
+ * per iteration (6 K).  Entries of iterations not yet run are NaN.  Syncs. */
+smc_status smc_trace(smc_ctx *ctx, double *score_k1, double *ess_k, double *est_6k);
+
+/* Score an arbitrary host particle set (n x 6) with the context's warp-and-
+ * score kernel and launch configuration, returning the raw sums per particle
+ * (n x 6 int64): masks (n, a, c, b_ov, 0, 0); images (n, sum s_fx, sum t,
+ * sum s_fx^2, sum t^2, sum s_fx t) with s_fx the interpolated source value in
+ * units of 1/256.  Uses the context's buffers; leaves the filter state alone
+ * but must not overlap smc_step on the same context.  Syncs. */
+smc_status smc_evaluate(smc_ctx *ctx, const double *states_n6, uint32_t n, int64_t *moments_n6);
+
+/* Replace the particle set (host N x 6) as if k_done iterations had run;
+ * for step-by-step replays and resumption.  Async. */
+smc_status smc_set_particles(smc_ctx *ctx, const double *states_n6, uint32_t k_done);
+
+/* Serialise / restore the whole filter state (particles, weights, estimate,
+ * trace, iteration count).  smc_get_state with buf == NULL returns the size in
+ * *len.  Restoring into a context made with the same inputs and parameters
+ * continues bit-identically.  Both sync. */
+smc_status smc_get_state(smc_ctx *ctx, void *buf, size_t *len);
+smc_status smc_set_state(smc_ctx *ctx, const void *buf, size_t len);
+
+/* Kernel timing.  With enable != 0 every warp-and-score launch and every
+ * filter launch of this context is bracketed by HIP events recorded on the
+ * context's stream.  smc_profile_read syncs, returns the summed durations
+ * (ms) and launch counts since the last read, and clears them.  Outputs may
+ * be NULL. */
+smc_status smc_profile(smc_ctx *ctx, int32_t enable);
+smc_status smc_profile_read(smc_ctx *ctx, double *score_ms, uint64_t *score_launches, double *filter_ms,
+                            uint64_t *filter_launches);
+
+/* Free everything the context owns (after syncing its stream).  NULL is a no-op. */
+void smc_destroy(smc_ctx *ctx);
+
+/* Methods (whole-cycle registration): apply one 3x4 target-mm -> source-mm
+ * matrix to n_frames source frames, writing uint8 volumes on the target grid
+ * (nx, ny, nz, spacing sx, sy, sz).  NEAREST copies the source byte; TRILINEAR
+ * writes floor(v + 0.5); target voxels whose source position falls outside
+ * the source grid get 0.  Frame f is read at src->data + f * src_frame_stride
+ * and written at dst + f * dst_frame_stride (bytes).  src->fov is ignored. */
+smc_status warp_apply(const smc_volume *src, const double mat3x4[12], int32_t interp, uint8_t *dst,
+                      int32_t nx, int32_t ny, int32_t nz, double sx, double sy, double sz, uint32_t n_frames,
+                      int64_t src_frame_stride, int64_t dst_frame_stride, void *hip_stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *smc_last_error(void);
+
+/* Library version string. */
+const char *smc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMC_H */

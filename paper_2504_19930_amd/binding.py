@@ -1,0 +1,289 @@
+"""ctypes binding of ``libsmc.so`` (declared in ``include/smc.h``).
+
+Argument marshalling only: every step of the registration runs in the HIP
+library.  PyTorch supplies device memory (uint8 tensors on a ROCm device) and
+the current stream.  The functions keep the C names (``smc_init``,
+``smc_step``, ``smc_estimate``, ``warp_apply`` ...); ``Registration`` wraps a
+context for convenience.  Importing works without a GPU, but every call that
+needs the library raises if it has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsmc.so")
+
+SMC_OK, SMC_EINVAL, SMC_ENOMEM, SMC_EDEVICE, SMC_ESTATE = 0, -1, -2, -3, -4
+SCORES = {"dice": 0, "ncc": 1, "ssd": 2}
+INTERPS = {"nearest": 0, "trilinear": 1}
+
+# every symbol include/smc.h declares
+EXPORTS = ("smc_init", "smc_reset", "smc_step", "smc_estimate", "smc_get_particles", "smc_trace",
+           "smc_evaluate", "smc_set_particles", "smc_get_state", "smc_set_state", "smc_destroy",
+           "warp_apply", "smc_last_error", "smc_version", "smc_profile", "smc_profile_read")
+
+
+class SmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"smc status {status}: {msg}")
+        self.status = status
+
+
+class SmcVolume(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("sx", C.c_double), ("sy", C.c_double), ("sz", C.c_double),
+                ("data", C.c_void_p), ("fov", C.c_void_p)]
+
+
+class SmcParams(C.Structure):
+    _fields_ = [("n_particles", C.c_uint32), ("n_iters", C.c_uint32), ("seed", C.c_uint64),
+                ("pair_id", C.c_uint32), ("score", C.c_int32), ("interp", C.c_int32),
+                ("x0", C.c_double * 6), ("limit", C.c_double * 6), ("sigma_score", C.c_double),
+                ("sigma0", C.c_double * 6), ("anneal", C.c_double), ("min_overlap_frac", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libsmc.so``; raise if it has not been built (no silent fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2504_19930_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, u32, u64, i32, i64, dp = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32, C.c_int64, C.c_double
+        P = C.POINTER
+        sig = {
+            "smc_init": [P(vp), P(SmcVolume), P(SmcVolume), P(SmcParams), vp],
+            "smc_reset": [vp, u64],
+            "smc_step": [vp, u32],
+            "smc_estimate": [vp, vp, vp, vp, vp],
+            "smc_get_particles": [vp, vp, vp, vp],
+            "smc_trace": [vp, vp, vp, vp],
+            "smc_evaluate": [vp, vp, u32, vp],
+            "smc_set_particles": [vp, vp, u32],
+            "smc_get_state": [vp, vp, P(C.c_size_t)],
+            "smc_set_state": [vp, vp, C.c_size_t],
+            "warp_apply": [P(SmcVolume), vp, i32, vp, i32, i32, i32, dp, dp, dp, u32, i64, i64, vp],
+            "smc_profile": [vp, i32],
+            "smc_profile_read": [vp, vp, vp, vp, vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.smc_destroy.argtypes = [vp]
+        L.smc_destroy.restype = None
+        L.smc_last_error.restype = C.c_char_p
+        L.smc_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != SMC_OK:
+        raise SmcError(status, lib().smc_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def volume(data, spacing=(1.0, 1.0, 1.0), fov=None) -> SmcVolume:
+    """Describe a device uint8 tensor of shape (nz, ny, nx) (C-contiguous)."""
+    import torch
+    for t in (data,) if fov is None else (data, fov):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.uint8 and t.dim() == 3
+                and t.is_contiguous()):
+            raise ValueError("volumes must be contiguous 3-D uint8 tensors on the GPU")
+    if fov is not None and fov.shape != data.shape:
+        raise ValueError("fov must have the volume's shape")
+    nz, ny, nx = data.shape
+    return SmcVolume(nx, ny, nz, *(float(s) for s in spacing), data.data_ptr(),
+                     None if fov is None else fov.data_ptr())
+
+
+def params(p: dict) -> SmcParams:
+    """Build smc_params from a dict (score / interp given by name)."""
+    out = SmcParams()
+    score = SCORES[p.get("score", "dice")]
+    out.n_particles = int(p["n_particles"])
+    out.n_iters = int(p["n_iters"])
+    out.seed = int(p.get("seed", 0))
+    out.pair_id = int(p.get("pair_id", 0))
+    out.score = score
+    out.interp = INTERPS[p.get("interp", "nearest" if score == 0 else "trilinear")]
+    out.x0[:] = [float(v) for v in p.get("x0", [0.0] * 6)]
+    out.limit[:] = [float(v) for v in p["limit"]]
+    out.sigma_score = float(p["sigma_score"])
+    out.sigma0[:] = [float(v) for v in p["sigma0"]]
+    out.anneal = float(p.get("anneal", 0.85))
+    out.min_overlap_frac = float(p.get("min_overlap_frac", 0.05))
+    return out
+
+
+# ------------------------------------------------------------------ C names
+
+def smc_init(src: SmcVolume, tgt: SmcVolume, prm: SmcParams, stream=None) -> C.c_void_p:
+    ctx = C.c_void_p()
+    _check(lib().smc_init(C.byref(ctx), C.byref(src), C.byref(tgt), C.byref(prm), _stream_handle(stream)))
+    return ctx
+
+
+def smc_reset(ctx, seed: int):
+    _check(lib().smc_reset(ctx, int(seed)))
+
+
+def smc_step(ctx, n_iters: int):
+    _check(lib().smc_step(ctx, int(n_iters)))
+
+
+def smc_estimate(ctx) -> dict:
+    p, M = np.zeros(6), np.zeros(12)
+    score, ess = C.c_double(), C.c_double()
+    _check(lib().smc_estimate(ctx, _ptr(p), _ptr(M), C.cast(C.byref(score), C.c_void_p),
+                              C.cast(C.byref(ess), C.c_void_p)))
+    return dict(params=p, matrix=M.reshape(3, 4), score=score.value, ess=ess.value)
+
+
+def smc_get_particles(ctx, n: int) -> dict:
+    x, lw, anc = np.zeros((n, 6)), np.zeros(n), np.zeros(n, np.int32)
+    _check(lib().smc_get_particles(ctx, _ptr(x), _ptr(lw), _ptr(anc)))
+    return dict(states=x, logw=lw, ancestors=anc)
+
+
+def smc_trace(ctx, n_iters: int) -> dict:
+    sc, ess, est = np.zeros(n_iters + 1), np.zeros(n_iters), np.zeros((n_iters, 6))
+    _check(lib().smc_trace(ctx, _ptr(sc), _ptr(ess), _ptr(est)))
+    return dict(score=sc, ess=ess, est=est)
+
+
+def smc_evaluate(ctx, states) -> np.ndarray:
+    x = np.ascontiguousarray(states, dtype=np.float64).reshape(-1, 6)
+    out = np.zeros((len(x), 6), np.int64)
+    _check(lib().smc_evaluate(ctx, _ptr(x), len(x), _ptr(out)))
+    return out
+
+
+def smc_set_particles(ctx, states, k_done: int):
+    x = np.ascontiguousarray(states, dtype=np.float64).reshape(-1, 6)
+    _check(lib().smc_set_particles(ctx, _ptr(x), int(k_done)))
+
+
+def smc_get_state(ctx) -> bytes:
+    n = C.c_size_t(0)
+    _check(lib().smc_get_state(ctx, None, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    _check(lib().smc_get_state(ctx, C.cast(buf, C.c_void_p), C.byref(n)))
+    return buf.raw[: n.value]
+
+
+def smc_set_state(ctx, blob: bytes):
+    buf = C.create_string_buffer(blob, len(blob))
+    _check(lib().smc_set_state(ctx, C.cast(buf, C.c_void_p), len(blob)))
+
+
+def smc_destroy(ctx):
+    if ctx:
+        lib().smc_destroy(ctx)
+
+
+def warp_apply(src: SmcVolume, matrix, interp: str, dst, spacing=(1.0, 1.0, 1.0), n_frames: int = 1,
+               src_frame_stride: int = 0, dst_frame_stride: int = 0, stream=None):
+    """Apply a 3x4 target-mm -> source-mm map to ``n_frames`` source frames,
+    writing into the device uint8 tensor ``dst`` of shape ([F,] nz, ny, nx)."""
+    M = np.ascontiguousarray(matrix, dtype=np.float64).reshape(12)
+    nz, ny, nx = dst.shape[-3:]
+    _check(lib().warp_apply(C.byref(src), _ptr(M), INTERPS[interp], C.c_void_p(dst.data_ptr()), nx, ny, nz,
+                            *(float(s) for s in spacing), int(n_frames), int(src_frame_stride),
+                            int(dst_frame_stride), _stream_handle(stream)))
+
+
+def smc_profile(ctx, enable: bool):
+    _check(lib().smc_profile(ctx, 1 if enable else 0))
+
+
+def smc_profile_read(ctx) -> dict:
+    sm, fm = C.c_double(), C.c_double()
+    sn, fn = C.c_uint64(), C.c_uint64()
+    _check(lib().smc_profile_read(ctx, C.cast(C.byref(sm), C.c_void_p), C.cast(C.byref(sn), C.c_void_p),
+                                  C.cast(C.byref(fm), C.c_void_p), C.cast(C.byref(fn), C.c_void_p)))
+    return dict(score_ms=sm.value, score_launches=sn.value, filter_ms=fm.value, filter_launches=fn.value)
+
+
+def version() -> str:
+    return lib().smc_version().decode()
+
+
+class Registration:
+    """One registration pair: owns an smc context on the current device."""
+
+    def __init__(self, src, tgt, prm: dict, spacing=(1.0, 1.0, 1.0), src_fov=None, tgt_fov=None,
+                 tgt_spacing=None, stream=None):
+        self._keep = (src, tgt, src_fov, tgt_fov)  # device memory must outlive the context
+        self.params = dict(prm)
+        self.n = int(prm["n_particles"])
+        self.K = int(prm["n_iters"])
+        self.src = volume(src, spacing, src_fov)
+        self.tgt = volume(tgt, spacing if tgt_spacing is None else tgt_spacing, tgt_fov)
+        self.ctx = smc_init(self.src, self.tgt, params(prm), stream)
+
+    def step(self, n=1):
+        smc_step(self.ctx, n)
+
+    def run(self):
+        smc_step(self.ctx, self.K)
+        return self.estimate()
+
+    def reset(self, seed):
+        smc_reset(self.ctx, seed)
+
+    def estimate(self):
+        return smc_estimate(self.ctx)
+
+    def particles(self):
+        return smc_get_particles(self.ctx, self.n)
+
+    def trace(self):
+        return smc_trace(self.ctx, self.K)
+
+    def evaluate(self, states):
+        return smc_evaluate(self.ctx, states)
+
+    def set_particles(self, states, k_done):
+        smc_set_particles(self.ctx, states, k_done)
+
+    def get_state(self):
+        return smc_get_state(self.ctx)
+
+    def set_state(self, blob):
+        smc_set_state(self.ctx, blob)
+
+    def profile(self, enable=True):
+        smc_profile(self.ctx, enable)
+
+    def profile_read(self):
+        return smc_profile_read(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            smc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

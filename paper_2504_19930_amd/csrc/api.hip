@@ -1,0 +1,604 @@
+// C ABI of the registration library (declared in include/smc.h): argument
+// checks, ownership of device workspaces, and the launch sequence of the
+// particle filter of Fig. 1.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "smc.h"
+
+using namespace smc;
+
+namespace {
+
+thread_local std::string g_err;
+
+smc_status fail(smc_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) return fail(SMC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+bool finite6(const double *v) {
+    for (int d = 0; d < 6; ++d)
+        if (!isfinite(v[d])) return false;
+    return true;
+}
+
+smc_status check_volume(const smc_volume *v, const char *name) {
+    if (!v) return fail(SMC_EINVAL, "%s is NULL", name);
+    if (!v->data) return fail(SMC_EINVAL, "%s->data is NULL", name);
+    if (v->nx < 1 || v->ny < 1 || v->nz < 1 || v->nx > 65535 || v->ny > 65535 || v->nz > 65535)
+        return fail(SMC_EINVAL, "%s dimensions %d x %d x %d outside 1..65535", name, v->nx, v->ny, v->nz);
+    if ((int64_t)v->nx * v->ny * v->nz >= ((int64_t)1 << 31))
+        return fail(SMC_EINVAL, "%s has 2^31 voxels or more", name);
+    if (!(v->sx > 0 && v->sy > 0 && v->sz > 0) || !isfinite(v->sx) || !isfinite(v->sy) || !isfinite(v->sz))
+        return fail(SMC_EINVAL, "%s spacing must be finite and positive", name);
+    return SMC_OK;
+}
+
+smc_status check_params(const smc_params *p) {
+    if (!p) return fail(SMC_EINVAL, "params is NULL");
+    if (p->n_particles < 1 || p->n_particles > 65536) return fail(SMC_EINVAL, "n_particles must be in 1..65536");
+    if (p->n_iters < 1 || p->n_iters > 100000) return fail(SMC_EINVAL, "n_iters must be in 1..100000");
+    if (p->score < SMC_SCORE_DICE || p->score > SMC_SCORE_SSD) return fail(SMC_EINVAL, "unknown score %d", p->score);
+    if (p->interp != SMC_INTERP_NEAREST && p->interp != SMC_INTERP_TRILINEAR)
+        return fail(SMC_EINVAL, "unknown interpolation %d", p->interp);
+    if (p->score == SMC_SCORE_DICE && p->interp != SMC_INTERP_NEAREST)
+        return fail(SMC_EINVAL, "the Dice score works on binary masks with nearest-neighbour sampling");
+    if (!finite6(p->x0) || !finite6(p->limit) || !finite6(p->sigma0))
+        return fail(SMC_EINVAL, "x0, limit and sigma0 must be finite");
+    for (int d = 0; d < 6; ++d) {
+        if (!(p->limit[d] > 0.0)) return fail(SMC_EINVAL, "limit[%d] must be positive", d);
+        if (p->sigma0[d] < 0.0) return fail(SMC_EINVAL, "sigma0[%d] must be non-negative", d);
+        if (fabs(p->x0[d]) + p->limit[d] > 1e6) return fail(SMC_EINVAL, "prior box too large on axis %d", d);
+    }
+    if (!(p->sigma_score > 0.0) || !isfinite(p->sigma_score)) return fail(SMC_EINVAL, "sigma_score must be positive");
+    if (!(p->anneal > 0.0 && p->anneal <= 1.0)) return fail(SMC_EINVAL, "anneal must be in (0, 1]");
+    if (!(p->min_overlap_frac >= 0.0 && p->min_overlap_frac <= 1.0))
+        return fail(SMC_EINVAL, "min_overlap_frac must be in [0, 1]");
+    return SMC_OK;
+}
+
+struct Stats {
+    uint64_t count, on;
+    double mu, sd;
+};
+
+// Mean and population standard deviation over the FOV from exact sums.
+Stats stats_from_sums(const unsigned long long s[4]) {
+    Stats r;
+    r.count = s[0];
+    r.on = s[1];
+    const double dn = (double)s[0];
+    const double m = (double)s[2] / dn;
+    const double var = (double)s[3] / dn - m * m;
+    r.mu = m;
+    r.sd = var > 0.0 ? sqrt(var) : 1.0;
+    return r;
+}
+
+}  // namespace
+
+struct smc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    smc_params p{};
+    int mode = kModeMask;
+    int32_t sn[3] = {0, 0, 0}, tn[3] = {0, 0, 0};
+    const uint8_t *src = nullptr, *src_fov = nullptr, *tgt = nullptr, *tgt_fov = nullptr;
+    uint8_t *src_prep = nullptr, *tgt_prep = nullptr, *src_ok = nullptr;
+    FilterState f{};
+    uint32_t k_done = 0;
+    smc_status sticky = SMC_OK;
+    std::string sticky_msg;
+    // smc_evaluate workspace
+    uint32_t eval_cap = 0;
+    double *x_eval = nullptr;
+    float *w_eval = nullptr;
+    unsigned long long *s_eval = nullptr;
+    std::vector<void *> allocs;
+    // kernel timing
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_score, ev_filter;
+
+    template <typename T>
+    smc_status alloc(T **out, size_t count) {
+        void *ptr = nullptr;
+        const size_t bytes = count * sizeof(T) > 0 ? count * sizeof(T) : 1;
+        if (hipMalloc(&ptr, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SMC_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+        }
+        allocs.push_back(ptr);
+        *out = static_cast<T *>(ptr);
+        return SMC_OK;
+    }
+
+    ScoreLaunch score_launch(const float *words, unsigned long long *sums, uint32_t p0, uint32_t np) const {
+        ScoreLaunch L;
+        L.mode = mode;
+        if (mode == kModeMask) {
+            L.src = src_prep;
+            L.src_ok = nullptr;
+            L.tgt = tgt_prep;
+            L.tgt_fov = nullptr;
+        } else {
+            L.src = src;
+            L.src_ok = src_ok;
+            L.tgt = tgt;
+            L.tgt_fov = tgt_fov;
+        }
+        L.words = words;
+        L.sums = sums;
+        for (int d = 0; d < 3; ++d) {
+            L.sn[d] = sn[d];
+            L.tn[d] = tn[d];
+        }
+        L.p0 = p0;
+        L.np = np;
+        return L;
+    }
+
+    smc_status mark(smc_status st) {
+        if (st != SMC_OK && sticky == SMC_OK) {
+            sticky = st;
+            sticky_msg = g_err;
+        }
+        return st;
+    }
+    smc_status check_sticky() {
+        if (sticky != SMC_OK) return fail(sticky, "context failed earlier: %s", sticky_msg.c_str());
+        return SMC_OK;
+    }
+};
+
+namespace {
+
+smc_status set_device(smc_ctx *c) {
+    HIP_TRY(hipSetDevice(c->device));
+    return SMC_OK;
+}
+
+hipEvent_t take_event(smc_ctx *c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch `fn` on the context stream, bracketed by events when profiling.
+template <typename F>
+hipError_t timed(smc_ctx *c, std::vector<std::pair<hipEvent_t, hipEvent_t>> &log, F fn) {
+    if (!c->profiling) return fn();
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, c->stream);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+    log.emplace_back(a, b);
+    return e;
+}
+
+smc_status launch_prior(smc_ctx *c) {
+    HIP_TRY(launch_fill_u64(c->f.sums, 6ull * (c->f.n + 1), c->stream));
+    HIP_TRY(launch_init_particles(c->f, c->stream));
+    c->k_done = 0;
+    return SMC_OK;
+}
+
+smc_status ensure_eval(smc_ctx *c, uint32_t n) {
+    if (n <= c->eval_cap) return SMC_OK;
+    // grow: old buffers stay in c->allocs until destroy (small)
+    smc_status st;
+    if ((st = c->alloc(&c->x_eval, 6ull * n)) != SMC_OK) return st;
+    if ((st = c->alloc(&c->w_eval, 12ull * n)) != SMC_OK) return st;
+    if ((st = c->alloc(&c->s_eval, 6ull * n)) != SMC_OK) return st;
+    c->eval_cap = n;
+    return SMC_OK;
+}
+
+// Score a device particle set with the context's kernel; sums into s_eval.
+smc_status evaluate_device(smc_ctx *c, const double *x_dev, uint32_t n) {
+    smc_status st = ensure_eval(c, n);
+    if (st != SMC_OK) return st;
+    HIP_TRY(launch_words(x_dev, n, c->f.geom, c->f.nearest, c->w_eval, c->stream));
+    HIP_TRY(launch_fill_u64(c->s_eval, 6ull * n, c->stream));
+    HIP_TRY(launch_score(c->score_launch(c->w_eval, c->s_eval, 0, n), c->stream));
+    return SMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *smc_last_error(void) { return g_err.c_str(); }
+
+const char *smc_version(void) { return "smcreg 0.1 (gfx950)"; }
+
+smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt, const smc_params *p,
+                    void *hip_stream) {
+    g_err.clear();
+    if (!out) return fail(SMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    smc_status st;
+    if ((st = check_volume(src, "src")) != SMC_OK) return st;
+    if ((st = check_volume(tgt, "tgt")) != SMC_OK) return st;
+    if ((st = check_params(p)) != SMC_OK) return st;
+
+    smc_ctx *c = new (std::nothrow) smc_ctx();
+    if (!c) return fail(SMC_ENOMEM, "host allocation failed");
+    c->stream = (hipStream_t)hip_stream;
+    c->p = *p;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(SMC_EDEVICE, "no HIP device");
+    }
+    c->sn[0] = src->nx; c->sn[1] = src->ny; c->sn[2] = src->nz;
+    c->tn[0] = tgt->nx; c->tn[1] = tgt->ny; c->tn[2] = tgt->nz;
+    c->src = src->data;
+    c->src_fov = src->fov;
+    c->tgt = tgt->data;
+    c->tgt_fov = tgt->fov;
+    c->mode = p->score == SMC_SCORE_DICE ? kModeMask
+              : (p->interp == SMC_INTERP_TRILINEAR ? kModeImageTrilinear : kModeImageNearest);
+    const int64_t vs = (int64_t)src->nx * src->ny * src->nz;
+    const int64_t vt = (int64_t)tgt->nx * tgt->ny * tgt->nz;
+    const uint32_t n = p->n_particles, K = p->n_iters;
+
+    auto bail = [&](smc_status s) {
+        smc_destroy(c);
+        return s;
+    };
+
+    // prepared inputs
+    if (c->mode == kModeMask) {
+        if ((st = c->alloc(&c->src_prep, vs)) != SMC_OK) return bail(st);
+        if ((st = c->alloc(&c->tgt_prep, vt)) != SMC_OK) return bail(st);
+        if (launch_prep_mask(src->data, src->fov, c->src_prep, vs, c->stream) != hipSuccess ||
+            launch_prep_mask(tgt->data, tgt->fov, c->tgt_prep, vt, c->stream) != hipSuccess)
+            return bail(fail(SMC_EDEVICE, "mask preparation launch failed"));
+    } else if (src->fov) {
+        if (c->mode == kModeImageTrilinear) {
+            if ((st = c->alloc(&c->src_ok, vs)) != SMC_OK) return bail(st);
+            if (launch_corner_valid(src->fov, c->src_ok, c->sn, c->stream) != hipSuccess)
+                return bail(fail(SMC_EDEVICE, "corner-validity launch failed"));
+        } else {
+            c->src_ok = const_cast<uint8_t *>(src->fov);
+        }
+    }
+
+    // exact per-volume sums -> statistics
+    unsigned long long *vsum = nullptr;
+    if ((st = c->alloc(&vsum, 8)) != SMC_OK) return bail(st);
+    unsigned long long hs[8];
+    if (launch_fill_u64(vsum, 8, c->stream) != hipSuccess ||
+        launch_volume_sums(tgt->data, tgt->fov, vt, vsum, c->stream) != hipSuccess ||
+        launch_volume_sums(src->data, src->fov, vs, vsum + 4, c->stream) != hipSuccess)
+        return bail(fail(SMC_EDEVICE, "volume statistics launch failed"));
+    if (hipMemcpyAsync(hs, vsum, sizeof hs, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return bail(fail(SMC_EDEVICE, "reading volume statistics failed: %s", hipGetErrorString(hipGetLastError())));
+    const Stats ts = stats_from_sums(hs), ss = stats_from_sums(hs + 4);
+    if (ts.count == 0) return bail(fail(SMC_EINVAL, "the target FOV is empty"));
+
+    FilterState &f = c->f;
+    f.n = n;
+    f.n_iters = K;
+    f.seed = p->seed;
+    f.pair = p->pair_id;
+    for (int d = 0; d < 3; ++d) f.geom.tn[d] = c->tn[d];
+    f.geom.ts[0] = tgt->sx; f.geom.ts[1] = tgt->sy; f.geom.ts[2] = tgt->sz;
+    f.geom.ss[0] = src->sx; f.geom.ss[1] = src->sy; f.geom.ss[2] = src->sz;
+    f.nearest = c->mode != kModeImageTrilinear;
+    f.sc.kind = p->score;
+    f.sc.t_on = ts.on;
+    f.sc.min_n = (uint64_t)ceil(p->min_overlap_frac * (double)ts.count);
+    f.sc.mu_s = ss.mu;
+    f.sc.sd_s = ss.sd;
+    f.sc.mu_t = ts.mu;
+    f.sc.sd_t = ts.sd;
+    f.sc.sigma = p->sigma_score;
+    for (int d = 0; d < 6; ++d) {
+        f.x0[d] = p->x0[d];
+        f.limit[d] = p->limit[d];
+        f.lo[d] = p->x0[d] - p->limit[d];
+        f.hi[d] = p->x0[d] + p->limit[d];
+        f.sigma0[d] = p->sigma0[d];
+    }
+    f.anneal = p->anneal;
+    if ((st = c->alloc(&f.x, 6ull * n)) != SMC_OK ||
+        (st = c->alloc(&f.x_next, 6ull * n)) != SMC_OK ||
+        (st = c->alloc(&f.words, 12ull * (n + 1))) != SMC_OK ||
+        (st = c->alloc(&f.sums, 6ull * (n + 1))) != SMC_OK ||
+        (st = c->alloc(&f.lw, n)) != SMC_OK || (st = c->alloc(&f.w, n)) != SMC_OK ||
+        (st = c->alloc(&f.cdf, n)) != SMC_OK || (st = c->alloc(&f.anc, n)) != SMC_OK ||
+        (st = c->alloc(&f.est, 6)) != SMC_OK || (st = c->alloc(&f.trace_score, K + 1ull)) != SMC_OK ||
+        (st = c->alloc(&f.trace_ess, K)) != SMC_OK || (st = c->alloc(&f.trace_est, 6ull * K)) != SMC_OK ||
+        (st = c->alloc(&f.flags, 4)) != SMC_OK)
+        return bail(st);
+    if ((st = launch_prior(c)) != SMC_OK) return bail(st);
+    *out = c;
+    return SMC_OK;
+}
+
+smc_status smc_reset(smc_ctx *c, uint64_t seed) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    c->f.seed = seed;
+    c->p.seed = seed;
+    return c->mark(launch_prior(c));
+}
+
+smc_status smc_step(smc_ctx *c, uint32_t n_iters) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((uint64_t)c->k_done + n_iters > c->f.n_iters)
+        return fail(SMC_ESTATE, "%u iterations requested, %u of %u already run", n_iters, c->k_done, c->f.n_iters);
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    const ScoreLaunch all = c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1);
+    const ScoreLaunch ghost = c->score_launch(c->f.words, c->f.sums, c->f.n, 1);
+    for (uint32_t it = 0; it < n_iters; ++it) {
+        const uint32_t k = c->k_done + 1;
+        hipError_t e = timed(c, c->ev_score, [&] { return launch_score(all, c->stream); });
+        if (e == hipSuccess) e = timed(c, c->ev_filter, [&] { return launch_filter(c->f, k, c->stream); });
+        if (e == hipSuccess && k == c->f.n_iters) {
+            e = launch_score(ghost, c->stream);
+            if (e == hipSuccess) e = launch_ghost_final(c->f, c->stream);
+        }
+        if (e != hipSuccess) return c->mark(fail(SMC_EDEVICE, "iteration %u launch failed: %s", k, hipGetErrorString(e)));
+        c->k_done = k;
+    }
+    return SMC_OK;
+}
+
+smc_status smc_evaluate(smc_ctx *c, const double *states, uint32_t n, int64_t *moments) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (n == 0) return SMC_OK;
+    if (!states || !moments) return fail(SMC_EINVAL, "states and moments must not be NULL");
+    for (uint64_t q = 0; q < 6ull * n; ++q)
+        if (!isfinite(states[q])) return fail(SMC_EINVAL, "state %llu is not finite", (unsigned long long)q);
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    if ((st = ensure_eval(c, n)) != SMC_OK) return c->mark(st);
+    if (hipMemcpyAsync(c->x_eval, states, 48ull * n, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return c->mark(fail(SMC_EDEVICE, "upload of states failed"));
+    if ((st = evaluate_device(c, c->x_eval, n)) != SMC_OK) return c->mark(st);
+    if (hipMemcpyAsync(moments, c->s_eval, 48ull * n, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return c->mark(fail(SMC_EDEVICE, "evaluation failed: %s", hipGetErrorString(hipGetLastError())));
+    return SMC_OK;
+}
+
+smc_status smc_estimate(smc_ctx *c, double params[6], double mat3x4[12], double *score, double *ess) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    double est[6], sc = NAN, e = NAN;
+    HIP_TRY(hipMemcpyAsync(est, c->f.est, sizeof est, hipMemcpyDeviceToHost, c->stream));
+    if (c->k_done >= 1)
+        HIP_TRY(hipMemcpyAsync(&e, c->f.trace_ess + (c->k_done - 1), sizeof e, hipMemcpyDeviceToHost, c->stream));
+    if (c->k_done == c->f.n_iters)
+        HIP_TRY(hipMemcpyAsync(&sc, c->f.trace_score + c->f.n_iters, sizeof sc, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (score && c->k_done < c->f.n_iters) {
+        int64_t m[6];
+        if ((st = smc_evaluate(c, est, 1, m)) != SMC_OK) return st;
+        sc = score_from_sums(m, c->f.sc);
+    }
+    if (params) memcpy(params, est, sizeof est);
+    if (mat3x4) rigid_matrix(est, c->f.geom, mat3x4);
+    if (score) *score = sc;
+    if (ess) *ess = e;
+    return SMC_OK;
+}
+
+smc_status smc_get_particles(smc_ctx *c, double *states, double *logw, int32_t *anc) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    const size_t n = c->f.n;
+    if (states) HIP_TRY(hipMemcpyAsync(states, c->f.x, 48 * n, hipMemcpyDeviceToHost, c->stream));
+    if (logw) HIP_TRY(hipMemcpyAsync(logw, c->f.lw, 8 * n, hipMemcpyDeviceToHost, c->stream));
+    if (anc) HIP_TRY(hipMemcpyAsync(anc, c->f.anc, 4 * n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SMC_OK;
+}
+
+smc_status smc_trace(smc_ctx *c, double *score_k1, double *ess_k, double *est_6k) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    const size_t K = c->f.n_iters;
+    if (score_k1) HIP_TRY(hipMemcpyAsync(score_k1, c->f.trace_score, 8 * (K + 1), hipMemcpyDeviceToHost, c->stream));
+    if (ess_k) HIP_TRY(hipMemcpyAsync(ess_k, c->f.trace_ess, 8 * K, hipMemcpyDeviceToHost, c->stream));
+    if (est_6k) HIP_TRY(hipMemcpyAsync(est_6k, c->f.trace_est, 48 * K, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SMC_OK;
+}
+
+smc_status smc_set_particles(smc_ctx *c, const double *states, uint32_t k_done) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (!states) return fail(SMC_EINVAL, "states is NULL");
+    if (k_done >= c->f.n_iters) return fail(SMC_EINVAL, "k_done must be below n_iters");
+    for (uint64_t q = 0; q < 6ull * c->f.n; ++q)
+        if (!isfinite(states[q])) return fail(SMC_EINVAL, "state %llu is not finite", (unsigned long long)q);
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    HIP_TRY(hipMemcpyAsync(c->f.x, states, 48ull * c->f.n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(launch_words(c->f.x, c->f.n, c->f.geom, c->f.nearest, c->f.words, c->stream));
+    HIP_TRY(launch_fill_u64(c->f.sums, 6ull * (c->f.n + 1), c->stream));
+    // the host copy must outlive the upload
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->k_done = k_done;
+    return SMC_OK;
+}
+
+namespace {
+struct StateHeader {
+    uint64_t magic, n, K, k_done;
+};
+const uint64_t kMagic = 0x534d435354415431ull;  // "SMCSTAT1"
+}  // namespace
+
+smc_status smc_get_state(smc_ctx *c, void *buf, size_t *len) {
+    if (!c || !len) return fail(SMC_EINVAL, "ctx and len must not be NULL");
+    const size_t n = c->f.n, K = c->f.n_iters;
+    const size_t need = sizeof(StateHeader) + 48 * n + 8 * n + 4 * n + 48 + 8 * (K + 1) + 8 * K + 48 * K + 4;
+    if (!buf) {
+        *len = need;
+        return SMC_OK;
+    }
+    if (*len < need) return fail(SMC_EINVAL, "buffer of %zu bytes, %zu needed", *len, need);
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    char *q = (char *)buf;
+    StateHeader h{kMagic, n, K, c->k_done};
+    memcpy(q, &h, sizeof h);
+    q += sizeof h;
+    struct Piece { const void *dev; size_t bytes; } pieces[] = {
+        {c->f.x, 48 * n}, {c->f.lw, 8 * n}, {c->f.anc, 4 * n}, {c->f.est, 48},
+        {c->f.trace_score, 8 * (K + 1)}, {c->f.trace_ess, 8 * K}, {c->f.trace_est, 48 * K}, {c->f.flags, 4}};
+    for (auto &pc : pieces) {
+        HIP_TRY(hipMemcpyAsync(q, pc.dev, pc.bytes, hipMemcpyDeviceToHost, c->stream));
+        q += pc.bytes;
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *len = need;
+    return SMC_OK;
+}
+
+smc_status smc_set_state(smc_ctx *c, const void *buf, size_t len) {
+    if (!c || !buf) return fail(SMC_EINVAL, "ctx and buf must not be NULL");
+    const size_t n = c->f.n, K = c->f.n_iters;
+    const size_t need = sizeof(StateHeader) + 48 * n + 8 * n + 4 * n + 48 + 8 * (K + 1) + 8 * K + 48 * K + 4;
+    if (len < need) return fail(SMC_EINVAL, "state of %zu bytes, %zu expected", len, need);
+    StateHeader h;
+    memcpy(&h, buf, sizeof h);
+    if (h.magic != kMagic || h.n != n || h.K != K || h.k_done > K)
+        return fail(SMC_EINVAL, "state does not match this context");
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    const char *q = (const char *)buf + sizeof h;
+    struct Piece { void *dev; size_t bytes; } pieces[] = {
+        {c->f.x, 48 * n}, {c->f.lw, 8 * n}, {c->f.anc, 4 * n}, {c->f.est, 48},
+        {c->f.trace_score, 8 * (K + 1)}, {c->f.trace_ess, 8 * K}, {c->f.trace_est, 48 * K}, {c->f.flags, 4}};
+    for (auto &pc : pieces) {
+        HIP_TRY(hipMemcpyAsync(pc.dev, q, pc.bytes, hipMemcpyHostToDevice, c->stream));
+        q += pc.bytes;
+    }
+    HIP_TRY(launch_words(c->f.x, c->f.n, c->f.geom, c->f.nearest, c->f.words, c->stream));
+    HIP_TRY(launch_words(c->f.est, 1, c->f.geom, c->f.nearest, c->f.words + 12 * n, c->stream));
+    HIP_TRY(launch_fill_u64(c->f.sums, 6ull * (n + 1), c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->k_done = (uint32_t)h.k_done;
+    return SMC_OK;
+}
+
+smc_status smc_profile(smc_ctx *c, int32_t enable) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    c->profiling = enable != 0;
+    return SMC_OK;
+}
+
+smc_status smc_profile_read(smc_ctx *c, double *score_ms, uint64_t *score_n, double *filter_ms,
+                            uint64_t *filter_n) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    smc_status st;
+    if ((st = set_device(c)) != SMC_OK) return st;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double sums[2] = {0.0, 0.0};
+    uint64_t counts[2] = {0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> *logs[2] = {&c->ev_score, &c->ev_filter};
+    for (int q = 0; q < 2; ++q) {
+        for (auto &pr : *logs[q]) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+            sums[q] += ms;
+            counts[q] += 1;
+            c->ev_pool.push_back(pr.first);
+            c->ev_pool.push_back(pr.second);
+        }
+        logs[q]->clear();
+    }
+    if (score_ms) *score_ms = sums[0];
+    if (score_n) *score_n = counts[0];
+    if (filter_ms) *filter_ms = sums[1];
+    if (filter_n) *filter_n = counts[1];
+    return SMC_OK;
+}
+
+void smc_destroy(smc_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (void *ptr : c->allocs) (void)hipFree(ptr);
+    for (auto *log : {&c->ev_score, &c->ev_filter})
+        for (auto &pr : *log) {
+            c->ev_pool.push_back(pr.first);
+            c->ev_pool.push_back(pr.second);
+        }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+smc_status warp_apply(const smc_volume *src, const double mat3x4[12], int32_t interp, uint8_t *dst, int32_t nx,
+                      int32_t ny, int32_t nz, double sx, double sy, double sz, uint32_t n_frames,
+                      int64_t src_frame_stride, int64_t dst_frame_stride, void *hip_stream) {
+    g_err.clear();
+    smc_status st;
+    if ((st = check_volume(src, "src")) != SMC_OK) return st;
+    if (!mat3x4 || !dst) return fail(SMC_EINVAL, "mat3x4 and dst must not be NULL");
+    for (int q = 0; q < 12; ++q)
+        if (!isfinite(mat3x4[q])) return fail(SMC_EINVAL, "matrix entry %d is not finite", q);
+    if (interp != SMC_INTERP_NEAREST && interp != SMC_INTERP_TRILINEAR)
+        return fail(SMC_EINVAL, "unknown interpolation %d", interp);
+    if (nx < 1 || ny < 1 || nz < 1 || nx > 65535 || ny > 65535 || nz > 65535)
+        return fail(SMC_EINVAL, "output dimensions out of range");
+    if (!(sx > 0 && sy > 0 && sz > 0)) return fail(SMC_EINVAL, "output spacing must be positive");
+    if (n_frames < 1 || n_frames > 65535) return fail(SMC_EINVAL, "n_frames must be in 1..65535");
+    const int64_t vs = (int64_t)src->nx * src->ny * src->nz, vt = (int64_t)nx * ny * nz;
+    if (n_frames > 1 && (src_frame_stride < vs || dst_frame_stride < vt))
+        return fail(SMC_EINVAL, "frame strides smaller than a frame");
+    const double ts[3] = {sx, sy, sz}, ss[3] = {src->sx, src->sy, src->sz};
+    float w[12];
+    words_from_matrix(mat3x4, ts, ss, interp == SMC_INTERP_NEAREST, w);
+    const int32_t sn[3] = {src->nx, src->ny, src->nz}, tn[3] = {nx, ny, nz};
+    hipError_t e = launch_warp_apply(src->data, sn, w, interp == SMC_INTERP_TRILINEAR, dst, tn, n_frames,
+                                     src_frame_stride, dst_frame_stride, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(SMC_EDEVICE, "warp_apply launch failed: %s", hipGetErrorString(e));
+    return SMC_OK;
+}
+
+}  // extern "C"

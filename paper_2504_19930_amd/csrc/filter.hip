@@ -1,0 +1,256 @@
+// Particle-filter kernels (Fig. 1): prior draw, and the per-iteration update
+// -> normalise / estimate -> systematic resampling -> prediction, fused into
+// one 1024-thread workgroup per registration pair.
+//
+// Determinism: log-weights come from exact integer sums; the resampling CDF
+// is an exact 64-bit integer prefix sum of q_i = floor(w_i 2^48) and every
+// pointer comparison is an exact 128-bit product, so the ancestors do not
+// depend on reduction order.  Only the estimate and the ESS use FP64 tree
+// sums.
+#include "internal.h"
+
+namespace smc {
+namespace {
+
+constexpr int kFT = 1024;  // filter workgroup
+constexpr int kFW = kFT / 64;
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_add(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u64(unsigned long long *p, uint64_t n) {
+    for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < n; q += (uint64_t)gridDim.x * blockDim.x)
+        p[q] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_words(const double *x, uint32_t n, Geom g, bool nearest, float *words) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double p[6];
+    for (int d = 0; d < 6; ++d) p[d] = x[6 * (size_t)i + d];
+    particle_words(p, g, nearest, words + 12 * (size_t)i);
+}
+
+// Prior: x_i = x0 + L (2u - 1), u from Philox (tag 0, three blocks).
+__global__ __launch_bounds__(256) void k_init(const FilterState f) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < f.n) {
+        double p[6];
+        for (uint32_t b = 0; b < 3; ++b) {
+            uint32_t r[4];
+            draw4(f.seed, i, 0u, f.pair, kTagInit, b, r);
+            const double ua = uniform53(r[0], r[1]), ub = uniform53(r[2], r[3]);
+            const int d0 = 2 * b, d1 = 2 * b + 1;
+            p[d0] = f.x0[d0] + f.limit[d0] * (2.0 * ua - 1.0);
+            p[d1] = f.x0[d1] + f.limit[d1] * (2.0 * ub - 1.0);
+        }
+        for (int d = 0; d < 6; ++d) f.x[6 * (size_t)i + d] = p[d];
+        particle_words(p, f.geom, f.nearest, f.words + 12 * (size_t)i);
+        f.lw[i] = 0.0;
+        f.anc[i] = -1;
+    }
+    if (i == 0) {
+        for (int d = 0; d < 6; ++d) f.est[d] = f.x0[d];
+        particle_words(f.x0, f.geom, f.nearest, f.words + 12 * (size_t)f.n);
+        f.flags[0] = 0;
+    }
+    const uint32_t nt = f.n_iters + 1;
+    for (uint32_t q = i; q < nt; q += gridDim.x * blockDim.x) {
+        f.trace_score[q] = __builtin_nan("");
+        if (q < f.n_iters) {
+            f.trace_ess[q] = __builtin_nan("");
+            for (int d = 0; d < 6; ++d) f.trace_est[6 * q + d] = __builtin_nan("");
+        }
+    }
+}
+
+__device__ __forceinline__ bool pointer_passed(unsigned long long c, unsigned __int128 scale,
+                                               unsigned __int128 rhs) {
+    return (unsigned __int128)c * scale > rhs;
+}
+
+__global__ __launch_bounds__(kFT) void k_filter(const FilterState f, const uint32_t k) {
+    __shared__ double red[kFW][8];
+    __shared__ double bcast[8];
+    __shared__ unsigned long long scan[kFT];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const uint32_t n = f.n;
+
+    // update: log-weights of the scores, and their maximum
+    double mx = -INFINITY;
+    for (uint32_t i = tid; i < n; i += kFT) {
+        int64_t m[6];
+        for (int q = 0; q < 6; ++q) m[q] = (int64_t)f.sums[6 * (size_t)i + q];
+        const double l = log_likelihood(score_from_sums(m, f.sc), f.sc);
+        f.lw[i] = l;
+        mx = fmax(mx, l);
+    }
+    if (tid == 0) {
+        int64_t m[6];
+        for (int q = 0; q < 6; ++q) m[q] = (int64_t)f.sums[6 * (size_t)n + q];
+        f.trace_score[k - 1] = score_from_sums(m, f.sc);
+    }
+    mx = wave_max(mx);
+    if (lane == 0) red[wave][0] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        double v = red[0][0];
+        for (int w = 1; w < kFW; ++w) v = fmax(v, red[w][0]);
+        bcast[0] = v;
+    }
+    __syncthreads();
+    const double M = bcast[0];
+    const bool degenerate = M == -INFINITY;
+
+    // normalise and estimate: w_i = exp(lw_i - M), weighted mean, ESS
+    double s = 0.0, s2 = 0.0, sx[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t i = tid; i < n; i += kFT) {
+        const double w = degenerate ? 1.0 : exp(f.lw[i] - M);
+        f.w[i] = w;
+        s += w;
+        s2 += w * w;
+        for (int d = 0; d < 6; ++d) sx[d] += w * f.x[6 * (size_t)i + d];
+    }
+    s = wave_add(s);
+    s2 = wave_add(s2);
+    for (int d = 0; d < 6; ++d) sx[d] = wave_add(sx[d]);
+    __syncthreads();
+    if (lane == 0) {
+        red[wave][0] = s;
+        red[wave][1] = s2;
+        for (int d = 0; d < 6; ++d) red[wave][2 + d] = sx[d];
+    }
+    __syncthreads();
+    if (tid < 8) {
+        double v = 0.0;
+        for (int w = 0; w < kFW; ++w) v += red[w][tid];
+        bcast[tid] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double est[6];
+        for (int d = 0; d < 6; ++d) {
+            est[d] = bcast[2 + d] / bcast[0];
+            f.est[d] = est[d];
+            f.trace_est[6 * (size_t)(k - 1) + d] = est[d];
+        }
+        f.trace_ess[k - 1] = (bcast[0] * bcast[0]) / bcast[1];
+        if (degenerate) f.flags[0] = 1;
+        particle_words(est, f.geom, f.nearest, f.words + 12 * (size_t)n);
+    }
+
+    if (k < f.n_iters) {
+        // exact integer CDF: contiguous chunk per thread, block scan of chunk sums
+        const uint32_t per = (n + kFT - 1) / kFT;
+        const uint32_t b0 = min(n, tid * per), b1 = min(n, b0 + per);
+        unsigned long long local = 0;
+        for (uint32_t i = b0; i < b1; ++i) local += (unsigned long long)floor(f.w[i] * 0x1p48);
+        scan[tid] = local;
+        __syncthreads();
+        for (int off = 1; off < kFT; off <<= 1) {
+            const unsigned long long v = tid >= off ? scan[tid - off] : 0ull;
+            __syncthreads();
+            scan[tid] += v;
+            __syncthreads();
+        }
+        unsigned long long run = scan[tid] - local;
+        for (uint32_t i = b0; i < b1; ++i) {
+            run += (unsigned long long)floor(f.w[i] * 0x1p48);
+            f.cdf[i] = run;
+        }
+        const unsigned long long Q = scan[kFT - 1];
+        __syncthreads();
+
+        uint32_t rw[4];
+        draw4(f.seed, 0u, k, f.pair, kTagResample, 0u, rw);
+        const unsigned __int128 scale = (unsigned __int128)n << 32;
+        double sg[6];
+        for (int d = 0; d < 6; ++d) {
+            double v = f.sigma0[d];
+            for (uint32_t m = 1; m < k; ++m) v = v * f.anneal;
+            sg[d] = v;
+        }
+        for (uint32_t j = tid; j < n; j += kFT) {
+            const unsigned __int128 rhs = ((((unsigned __int128)j) << 32) + rw[0]) * (unsigned __int128)Q;
+            uint32_t lo = 0, hi = n - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (pointer_passed(f.cdf[mid], scale, rhs)) hi = mid;
+                else lo = mid + 1;
+            }
+            f.anc[j] = (int32_t)lo;
+            // prediction: reflected annealed Gaussian random walk (Box-Muller)
+            double g[6];
+            for (uint32_t b = 0; b < 3; ++b) {
+                uint32_t r[4];
+                draw4(f.seed, j, k, f.pair, kTagPerturb, b, r);
+                const double u1 = uniform53(r[0], r[1]), u2 = uniform53(r[2], r[3]);
+                const double rad = sqrt(-2.0 * log(u1));
+                const double th = 6.283185307179586 * u2;
+                g[2 * b] = rad * cos(th);
+                g[2 * b + 1] = rad * sin(th);
+            }
+            for (int d = 0; d < 6; ++d)
+                f.x_next[6 * (size_t)j + d] = reflect_into(f.x[6 * (size_t)lo + d] + sg[d] * g[d], f.lo[d], f.hi[d]);
+        }
+        __syncthreads();
+        for (uint32_t j = tid; j < n; j += kFT) {
+            double p[6];
+            for (int d = 0; d < 6; ++d) {
+                p[d] = f.x_next[6 * (size_t)j + d];
+                f.x[6 * (size_t)j + d] = p[d];
+            }
+            particle_words(p, f.geom, f.nearest, f.words + 12 * (size_t)j);
+        }
+    }
+    // clear the sums for the next evaluation
+    for (uint32_t q = tid; q < 6 * (n + 1); q += kFT) f.sums[q] = 0ull;
+}
+
+__global__ void k_ghost_final(const FilterState f) {
+    int64_t m[6];
+    for (int q = 0; q < 6; ++q) m[q] = (int64_t)f.sums[6 * (size_t)f.n + q];
+    f.trace_score[f.n_iters] = score_from_sums(m, f.sc);
+    for (int q = 0; q < 6; ++q) f.sums[6 * (size_t)f.n + q] = 0ull;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    uint64_t b = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)(b < 2048 ? b : 2048)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_words(const double *x, uint32_t n, const Geom &g, bool nearest, float *words, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_words, dim3((n + 255) / 256), dim3(256), 0, s, x, n, g, nearest, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_particles(const FilterState &f, hipStream_t s) {
+    const uint32_t n = f.n > f.n_iters + 1 ? f.n : f.n_iters + 1;
+    hipLaunchKernelGGL(k_init, dim3((n + 255) / 256), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter(const FilterState &f, uint32_t k, hipStream_t s) {
+    hipLaunchKernelGGL(k_filter, dim3(1), dim3(kFT), 0, s, f, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_ghost_final(const FilterState &f, hipStream_t s) {
+    hipLaunchKernelGGL(k_ghost_final, dim3(1), dim3(1), 0, s, f);
+    return hipGetLastError();
+}
+
+}  // namespace smc

@@ -1,0 +1,93 @@
+// Once-per-pair preparation: packed mask / FOV bytes, the trilinear
+// corner-validity mask of the source FOV, and exact per-volume sums
+// (FOV voxel count, nonzero count, sum and sum of squares) from which the
+// host derives |T| for Dice, the minimum overlap and the mean-0 / std-1
+// normalisation statistics of Implementation Details.
+#include "internal.h"
+
+namespace smc {
+namespace {
+
+// bit 0: inside the FOV (no FOV = everywhere); bit 1: nonzero and inside.
+__global__ void k_prep_mask(const uint8_t *vol, const uint8_t *fov, uint8_t *out, int64_t n) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t in = fov ? (fov[q] != 0) : 1u;
+        out[q] = (uint8_t)(in | ((in && vol[q] != 0) ? 2u : 0u));
+    }
+}
+
+// A trilinear sample with base corner (i, j, k) is valid iff all eight
+// (edge-clamped) corners are inside the FOV.
+__global__ void k_corner_valid(const uint8_t *fov, uint8_t *out, int32_t nx, int32_t ny, int32_t nz) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = (int32_t)(q % nx);
+        const int32_t j = (int32_t)((q / nx) % ny);
+        const int32_t k = (int32_t)(q / ((int64_t)nx * ny));
+        const int64_t dx = i + 1 < nx ? 1 : 0;
+        const int64_t dy = j + 1 < ny ? nx : 0;
+        const int64_t dz = k + 1 < nz ? (int64_t)nx * ny : 0;
+        const bool ok = fov[q] && fov[q + dx] && fov[q + dy] && fov[q + dx + dy] && fov[q + dz] &&
+                        fov[q + dz + dx] && fov[q + dz + dy] && fov[q + dz + dy + dx];
+        out[q] = ok ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_volume_sums(const uint8_t *vol, const uint8_t *fov, int64_t n,
+                                                     unsigned long long *out) {
+    unsigned long long c = 0, o = 0, s1 = 0, s2 = 0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        if (fov && fov[q] == 0) continue;
+        const unsigned long long v = vol[q];
+        c += 1;
+        o += v != 0;
+        s1 += v;
+        s2 += v * v;
+    }
+    __shared__ unsigned long long red[4][4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_xor(c, off);
+        o += __shfl_xor(o, off);
+        s1 += __shfl_xor(s1, off);
+        s2 += __shfl_xor(s2, off);
+    }
+    const int wave = threadIdx.x / 64;
+    if (threadIdx.x % 64 == 0) {
+        red[wave][0] = c;
+        red[wave][1] = o;
+        red[wave][2] = s1;
+        red[wave][3] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        unsigned long long s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        atomicAdd(out + threadIdx.x, s);
+    }
+}
+
+unsigned blocks_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+}  // namespace
+
+hipError_t launch_prep_mask(const uint8_t *vol, const uint8_t *fov, uint8_t *out, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_prep_mask, dim3(blocks_for(n)), dim3(256), 0, s, vol, fov, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_corner_valid(const uint8_t *fov, uint8_t *out, const int32_t n[3], hipStream_t s) {
+    const int64_t tot = (int64_t)n[0] * n[1] * n[2];
+    hipLaunchKernelGGL(k_corner_valid, dim3(blocks_for(tot)), dim3(256), 0, s, fov, out, n[0], n[1], n[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_volume_sums(const uint8_t *vol, const uint8_t *fov, int64_t n, unsigned long long *out,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_volume_sums, dim3(blocks_for(n)), dim3(256), 0, s, vol, fov, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace smc

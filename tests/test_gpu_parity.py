@@ -1,0 +1,273 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs.  Integer sums (mask counts, fixed-point image moments),
+the prior draw and the resampling ancestors must match bit for bit;
+floating-point states and estimates within the stated tolerances; the final
+transform within 0.05 mm and 0.02 deg.  Both sides run independently from the
+same seeds -- nothing the GPU produces is fed to the oracle."""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2504_19930_amd import config
+
+pytestmark = pytest.mark.gpu
+
+TOL_MM, TOL_DEG = 0.05, 0.02
+
+
+@pytest.fixture(scope="module")
+def smc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_19930_amd import binding
+    binding.lib()  # raises if the HIP library is missing
+    return binding
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def geodesic_deg(p, q, orc):
+    R1, R2 = orc.euler_R(p[:3]), orc.euler_R(q[:3])
+    return math.degrees(math.acos(max(-1.0, min(1.0, (np.trace(R1.T @ R2) - 1) / 2))))
+
+
+def _reg(smc, pair, prm, src_fov=None, tgt_fov=None, spacing=(1.0, 1.0, 1.0), tgt_spacing=None):
+    return smc.Registration(dev(pair["src"]), dev(pair["tgt"]), prm, spacing=spacing,
+                            src_fov=None if src_fov is None else dev(src_fov),
+                            tgt_fov=None if tgt_fov is None else dev(tgt_fov), tgt_spacing=tgt_spacing)
+
+
+def _random_states(n, rot_deg, trans, seed):
+    rng = np.random.default_rng(seed)
+    return np.concatenate([np.deg2rad(rng.uniform(-rot_deg, rot_deg, (n, 3))),
+                           rng.uniform(-trans, trans, (n, 3))], 1)
+
+
+def _oracle_sums(orc, s, t, x, mode):
+    out = np.zeros((len(x), 6), np.int64)
+    for i, p in enumerate(x):
+        if mode == "mask":
+            out[i, :4] = orc.mask_counts(s, t, orc.recipe_words(p, s, t, nn=True)).astype(np.int64)
+        else:
+            tri = mode == "trilinear"
+            out[i] = orc.image_moments(s, t, orc.recipe_words(p, s, t, nn=not tri), tri)
+    return out
+
+
+def _assert_final_close(orc, est_gpu, est_orc):
+    assert np.linalg.norm(est_gpu[3:] - est_orc[3:]) <= TOL_MM
+    assert geodesic_deg(est_gpu, est_orc, orc) <= TOL_DEG
+
+
+# ------------------------------------------------------------------ prior and scoring sums
+
+def test_prior_draw_bit_exact(smc, orc):
+    pair = synth.shell_pair(seed=1)
+    prm = config.workload_params("shell64")
+    r = _reg(smc, pair, prm)
+    got = r.particles()
+    assert np.array_equal(got["states"], orc.init_particles(prm))
+    assert np.all(got["ancestors"] == -1)
+
+
+def test_mask_sums_bit_exact_shell64(smc, orc):
+    pair = synth.shell_pair(seed=1)
+    r = _reg(smc, pair, config.workload_params("shell64"))
+    x = np.vstack([np.zeros(6), pair["gt"], _random_states(70, 15, 8, 3)])
+    got = r.evaluate(x)
+    want = _oracle_sums(orc, orc.Volume(pair["src"]), orc.Volume(pair["tgt"]), x, "mask")
+    assert np.array_equal(got, want)
+    # identity on identical masks: every count equals |T|
+    same = _reg(smc, dict(src=pair["tgt"], tgt=pair["tgt"]), config.workload_params("shell64"))
+    c = same.evaluate(np.zeros((1, 6)))[0]
+    assert c[0] == pair["tgt"].size and c[1] == c[2] == c[3] == pair["tgt"].sum()
+
+
+def _blob_fov(shape_zyx, seed, frac=0.7):
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(*[np.linspace(-1, 1, n) for n in shape_zyx], indexing="ij")
+    c = rng.uniform(-0.3, 0.3, 3)
+    return (((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) < frac).astype(np.uint8)
+
+
+@pytest.mark.parametrize("with_fov", [False, True])
+def test_mask_sums_ragged_anisotropic(smc, orc, with_fov):
+    rng = np.random.default_rng(21)
+    src = (rng.random((23, 29, 37)) < 0.3).astype(np.uint8)
+    tgt = (rng.random((19, 27, 41)) < 0.3).astype(np.uint8)
+    sfov = _blob_fov(src.shape, 1) if with_fov else None
+    tfov = _blob_fov(tgt.shape, 2) if with_fov else None
+    ss, ts = (0.9, 1.1, 0.8), (1.0, 1.2, 0.7)
+    prm = config.default_params("dice", 40, 3, 15.0, 4.0)
+    r = _reg(smc, dict(src=src, tgt=tgt), prm, src_fov=sfov, tgt_fov=tfov, spacing=ss, tgt_spacing=ts)
+    x = _random_states(40, 15, 4, 5)
+    got = r.evaluate(x)
+    want = _oracle_sums(orc, orc.Volume(src, ss, sfov), orc.Volume(tgt, ts, tfov), x, "mask")
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("interp", ["trilinear", "nearest"])
+@pytest.mark.parametrize("with_fov", [False, True])
+def test_image_sums_bit_exact(smc, orc, interp, with_fov):
+    pair = synth.speckle_pair(side=45, seed=7, cone=with_fov, trans=4.0)
+    src, tgt = pair["src"], pair["tgt"][:33, 3:41, :]  # ragged, different target shape
+    tgt = np.ascontiguousarray(tgt)
+    sfov = pair.get("src_fov") if with_fov else None
+    tfov = _blob_fov(tgt.shape, 3) if with_fov else None
+    prm = config.default_params("ncc", 48, 3, 20.0, 4.0, interp=interp)
+    r = _reg(smc, dict(src=src, tgt=tgt), prm, src_fov=sfov, tgt_fov=tfov)
+    x = np.vstack([np.zeros(6), _random_states(47, 20, 4, 6)])
+    got = r.evaluate(x)
+    want = _oracle_sums(orc, orc.Volume(src, fov=sfov), orc.Volume(tgt, fov=tfov), x, interp)
+    assert np.array_equal(got, want)
+
+
+# ------------------------------------------------------------------ whole filter
+
+def _compare_runs(smc, orc, pair, prm, src_fov=None):
+    r = _reg(smc, pair, prm, src_fov=src_fov)
+    r.run()
+    g_est = r.estimate()
+    g_part = r.particles()
+    g_tr = r.trace()
+    o = orc.smc_run(orc.Volume(pair["src"], fov=src_fov), orc.Volume(pair["tgt"]), prm)
+    # ancestors: integer CDF -> identical
+    assert np.array_equal(g_part["ancestors"], o["ancestors"])
+    # states: equal up to the last bits of the FP64 Box-Muller transcendentals
+    assert np.allclose(g_part["states"], o["states"], rtol=0, atol=1e-12)
+    assert np.allclose(g_part["logw"], o["logw"], rtol=1e-12, atol=1e-12)
+    assert np.allclose(g_tr["score"], o["trace_score"], rtol=1e-12, atol=1e-15)
+    assert np.allclose(g_tr["ess"], o["trace_ess"], rtol=1e-9)
+    assert np.allclose(g_tr["est"], o["trace_est"], rtol=0, atol=1e-12)
+    _assert_final_close(orc, g_est["params"], o["est"])
+    assert np.allclose(g_est["params"], o["est"], atol=1e-12)
+    zg, zo = g_est["score"], o["trace_score"][-1]
+    assert zg == zo or abs(zg - zo) <= 1e-12
+    return r, o
+
+
+def test_full_filter_shell64_matches_oracle(smc, orc):
+    """The 64^3 shell workload end to end: N = 256, K = 10, Dice."""
+    pair = synth.shell_pair(seed=1)
+    _compare_runs(smc, orc, pair, config.workload_params("shell64"))
+
+
+def test_full_filter_image_ncc_and_ssd(smc, orc):
+    pair = synth.speckle_pair(side=40, seed=9, trans=3.0)
+    for score in ("ncc", "ssd"):
+        prm = config.default_params(score, 192, 5, 20.0, 3.0, seed=4)
+        _compare_runs(smc, orc, pair, prm, src_fov=pair["src_fov"])
+
+
+def test_degenerate_sizes(smc, orc):
+    pair = synth.shell_pair(seed=2, side=24)
+    _compare_runs(smc, orc, pair, config.default_params("dice", 1, 3, 15.0, 3.0, seed=3))
+    _compare_runs(smc, orc, pair, config.default_params("dice", 33, 1, 15.0, 3.0, seed=3))
+    # no overlap anywhere: every weight -inf -> uniform weights, flagged, still finite
+    far = config.default_params("ncc", 16, 3, 1.0, 1.0, seed=1, x0=[0, 0, 0, 500.0, 0, 0])
+    spk = synth.speckle_pair(side=16, seed=3, cone=False)
+    r, o = _compare_runs(smc, orc, spk, far)
+    assert o["degenerate"] and np.all(np.isfinite(r.particles()["states"]))
+
+
+def test_stepwise_equals_single_call_and_state_roundtrip(smc, orc):
+    pair = synth.shell_pair(seed=5, side=40)
+    prm = config.default_params("dice", 128, 6, 15.0, 5.0, seed=11)
+    a = _reg(smc, pair, prm)
+    a.run()
+    b = _reg(smc, pair, prm)
+    b.step(2)
+    blob = b.get_state()
+    b.step(4)
+    c = _reg(smc, pair, prm)
+    c.set_state(blob)
+    c.step(4)
+    for r in (b, c):
+        assert np.array_equal(r.particles()["states"], a.particles()["states"])
+        assert np.array_equal(r.estimate()["params"], a.estimate()["params"])
+    with pytest.raises(smc.SmcError):
+        c.step(1)  # past K
+    c.reset(11)
+    c.run()
+    assert np.array_equal(c.particles()["states"], a.particles()["states"])
+
+
+# ------------------------------------------------------------------ warp_apply
+
+@pytest.mark.parametrize("interp", ["nearest", "trilinear"])
+def test_warp_apply_bit_exact(smc, orc, interp):
+    import torch
+    rng = np.random.default_rng(13)
+    frames = rng.integers(0, 256, (3, 21, 26, 31)).astype(np.uint8)
+    ss, ts, tshape = (0.9, 1.1, 1.3), (1.0, 1.0, 1.2), (33, 24, 19)
+    M = orc.phys_matrix([0.2, -0.1, 0.15, 1.5, -2.0, 0.7], tshape, ts)
+    src = dev(frames)
+    out = torch.zeros((3, tshape[2], tshape[1], tshape[0]), dtype=torch.uint8, device="cuda")
+    vol = smc.volume(src[0], ss)
+    smc.warp_apply(vol, M, interp, out, spacing=ts, n_frames=3, src_frame_stride=frames[0].size,
+                   dst_frame_stride=int(np.prod(tshape)))
+    got = out.cpu().numpy()
+    for f in range(3):
+        want = orc.warp_apply(orc.Volume(frames[f], ss), M, interp == "trilinear", tshape, ts)
+        assert np.array_equal(got[f], want), f
+
+
+# ------------------------------------------------------------------ full-size workloads
+
+def test_speckle160_full_size_sampled(smc, orc):
+    """The throughput workload at full size (160^3 images with a cone FOV,
+    N = 2048, NCC, trilinear) in the benchmark's launch configuration: the
+    prior set is bit-exact, sampled particles' sums are bit-exact, and the
+    filter's outputs hold the properties any run must."""
+    pair = synth.speckle_pair(side=160, seed=2)
+    prm = config.workload_params("speckle160")
+    r = _reg(smc, pair, prm, src_fov=pair["src_fov"])
+    x0 = r.particles()["states"]
+    assert np.array_equal(x0, orc.init_particles(prm))
+    got = r.evaluate(x0)
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(len(x0), 5, replace=False))
+    s, t = orc.Volume(pair["src"], fov=pair["src_fov"]), orc.Volume(pair["tgt"])
+    assert np.array_equal(got[idx], _oracle_sums(orc, s, t, x0[idx], "trilinear"))
+    r.run()
+    tr = r.trace()
+    est = r.estimate()
+    assert np.all(np.isfinite(tr["score"])) and np.all((tr["ess"] >= 1.0) & (tr["ess"] <= prm["n_particles"]))
+    assert tr["score"][-1] >= tr["score"][0]
+    lim = np.asarray(prm["limit"])
+    assert np.all(np.abs(est["params"]) <= lim + 1e-12)
+    # the estimate's score from the oracle matches the GPU's own
+    pb = orc.Problem(s, t)
+    z = pb.score(prm, est["params"][None])[0]
+    assert abs(z - est["score"]) <= 1e-12
+
+
+def test_lv224_full_size_sampled_and_warp_all_frames(smc, orc):
+    import torch
+    seq = synth.lv_sequence(seed=3, frames=[0, 5, 10], n_frames=20)
+    prm = config.workload_params("lv224", n_iters=6)
+    r = _reg(smc, seq, prm)
+    x0 = r.particles()["states"]
+    assert np.array_equal(x0, orc.init_particles(prm))
+    got = r.evaluate(x0[:64])
+    s, t = orc.Volume(seq["src"]), orc.Volume(seq["tgt"])
+    idx = np.array([0, 17, 63])
+    assert np.array_equal(got[idx], _oracle_sums(orc, s, t, x0[idx], "mask"))
+    r.run()
+    M = r.estimate()["matrix"]
+    shape = seq["shape_xyz"]
+    for frames, interp in ((seq["src_masks"], "nearest"), (seq["src_speckle"], "trilinear")):
+        src = dev(frames)
+        out = torch.zeros_like(src)
+        smc.warp_apply(smc.volume(src[0]), M, interp, out, n_frames=len(frames),
+                       src_frame_stride=frames[0].size, dst_frame_stride=frames[0].size)
+        o = out.cpu().numpy()
+        for f in (0, len(frames) - 1):
+            assert np.array_equal(o[f], orc.warp_apply(frames[f], M, interp == "trilinear", shape))
