@@ -132,6 +132,16 @@ smc_status smc_set_particles(smc_ctx *ctx, const double *states_n6, uint32_t k_d
 smc_status smc_get_state(smc_ctx *ctx, void *buf, size_t *len);
 smc_status smc_set_state(smc_ctx *ctx, const void *buf, size_t len);
 
+/* Launch tuning of the warp-and-score kernel; results do not depend on it.
+ * layout: trilinear source layout, 0 raw bytes (eight gathers per sample),
+ * 1 x-pairs (uint16, four), 2 2x2 quads (uint32, two), 3 2x2x2 octets
+ * (uint64, one); packed layouts cost 2, 4 or 8 bytes per source voxel of
+ * device memory, prepared on the stream.  particles_per_group: particles
+ * sharing one pass over a target column, 4, 8 or 16.  A negative value
+ * keeps the current setting.  Defaults come from measurements on MI355X. */
+smc_status smc_set_tuning(smc_ctx *ctx, int32_t layout, int32_t particles_per_group);
+smc_status smc_get_tuning(smc_ctx *ctx, int32_t *layout, int32_t *particles_per_group);
+
 /* Kernel timing.  With enable != 0 every warp-and-score launch and every
  * filter launch of this context is bracketed by HIP events recorded on the
  * context's stream.  smc_profile_read syncs, returns the summed durations
@@ -153,6 +163,29 @@ void smc_destroy(smc_ctx *ctx);
 smc_status warp_apply(const smc_volume *src, const double mat3x4[12], int32_t interp, uint8_t *dst,
                       int32_t nx, int32_t ny, int32_t nz, double sx, double sy, double sz, uint32_t n_frames,
                       int64_t src_frame_stride, int64_t dst_frame_stride, void *hip_stream);
+
+/* ---- Batches: many registration pairs of uneven size and particle count
+ * run together.  Every pair behaves exactly as its own smc_init /
+ * smc_step context would (the pair id sits in the Philox counter), but the
+ * warp-and-score work of all pairs of a class (masks; trilinear images)
+ * shares one persistent launch per iteration, the filters of all pairs
+ * share one launch, and the whole run -- prior draws, every iteration,
+ * final scores -- is captured once into a HIP graph and replayed by each
+ * smc_batch_run.  The batch owns a stream of its own; smc_batch_run orders
+ * it after the caller's stream and the caller's stream after it. */
+typedef struct smc_batch smc_batch;
+
+/* src, tgt and p are arrays of n_pairs (1 .. 4096).  Syncs once per pair. */
+smc_status smc_batch_init(smc_batch **out, uint32_t n_pairs, const smc_volume *src, const smc_volume *tgt,
+                          const smc_params *p, void *hip_stream);
+/* New prior seeds for the next run (one per pair; NULL keeps them). */
+smc_status smc_batch_set_seeds(smc_batch *b, const uint64_t *seeds);
+/* Run every pair's full registration (one graph launch).  Async. */
+smc_status smc_batch_run(smc_batch *b);
+/* The context of pair i, for smc_estimate / smc_get_particles / smc_trace
+ * (do not step or destroy it); NULL if i is out of range. */
+smc_ctx *smc_batch_pair(smc_batch *b, uint32_t i);
+void smc_batch_destroy(smc_batch *b);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *smc_last_error(void);

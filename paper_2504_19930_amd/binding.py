@@ -25,7 +25,9 @@ INTERPS = {"nearest": 0, "trilinear": 1}
 # every symbol include/smc.h declares
 EXPORTS = ("smc_init", "smc_reset", "smc_step", "smc_estimate", "smc_get_particles", "smc_trace",
            "smc_evaluate", "smc_set_particles", "smc_get_state", "smc_set_state", "smc_destroy",
-           "warp_apply", "smc_last_error", "smc_version", "smc_profile", "smc_profile_read")
+           "warp_apply", "smc_last_error", "smc_version", "smc_profile", "smc_profile_read",
+           "smc_set_tuning", "smc_get_tuning", "smc_batch_init", "smc_batch_set_seeds", "smc_batch_run",
+           "smc_batch_pair", "smc_batch_destroy")
 
 
 class SmcError(RuntimeError):
@@ -73,6 +75,11 @@ def lib():
             "warp_apply": [P(SmcVolume), vp, i32, vp, i32, i32, i32, dp, dp, dp, u32, i64, i64, vp],
             "smc_profile": [vp, i32],
             "smc_profile_read": [vp, vp, vp, vp, vp],
+            "smc_set_tuning": [vp, i32, i32],
+            "smc_get_tuning": [vp, vp, vp],
+            "smc_batch_init": [P(vp), u32, vp, vp, vp, vp],
+            "smc_batch_set_seeds": [vp, vp],
+            "smc_batch_run": [vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -80,6 +87,10 @@ def lib():
             fn.restype = C.c_int
         L.smc_destroy.argtypes = [vp]
         L.smc_destroy.restype = None
+        L.smc_batch_pair.argtypes = [vp, u32]
+        L.smc_batch_pair.restype = vp
+        L.smc_batch_destroy.argtypes = [vp]
+        L.smc_batch_destroy.restype = None
         L.smc_last_error.restype = C.c_char_p
         L.smc_version.restype = C.c_char_p
         _lib = L
@@ -223,6 +234,21 @@ def smc_profile_read(ctx) -> dict:
     return dict(score_ms=sm.value, score_launches=sn.value, filter_ms=fm.value, filter_launches=fn.value)
 
 
+LAYOUTS = {"raw": 0, "pairx": 1, "quadxy": 2, "oct": 3}
+
+
+def smc_set_tuning(ctx, layout=None, particles_per_group=None):
+    lay = -1 if layout is None else (LAYOUTS[layout] if isinstance(layout, str) else int(layout))
+    pt = -1 if particles_per_group is None else int(particles_per_group)
+    _check(lib().smc_set_tuning(ctx, lay, pt))
+
+
+def smc_get_tuning(ctx) -> dict:
+    lay, pt = C.c_int32(), C.c_int32()
+    _check(lib().smc_get_tuning(ctx, C.cast(C.byref(lay), C.c_void_p), C.cast(C.byref(pt), C.c_void_p)))
+    return dict(layout=lay.value, particles_per_group=pt.value)
+
+
 def version() -> str:
     return lib().smc_version().decode()
 
@@ -271,6 +297,12 @@ class Registration:
     def set_state(self, blob):
         smc_set_state(self.ctx, blob)
 
+    def tune(self, layout=None, particles_per_group=None):
+        smc_set_tuning(self.ctx, layout, particles_per_group)
+
+    def tuning(self):
+        return smc_get_tuning(self.ctx)
+
     def profile(self, enable=True):
         smc_profile(self.ctx, enable)
 
@@ -281,6 +313,60 @@ class Registration:
         if self.ctx:
             smc_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many registration pairs run as one graph launch (smc_batch_*).  Each
+    pair is a dict with src, tgt (device uint8 tensors), params (dict) and
+    optional src_fov, tgt_fov, spacing, tgt_spacing."""
+
+    def __init__(self, pairs, stream=None):
+        n = len(pairs)
+        self._keep = [(q["src"], q["tgt"], q.get("src_fov"), q.get("tgt_fov")) for q in pairs]
+        srcs = (SmcVolume * n)()
+        tgts = (SmcVolume * n)()
+        prms = (SmcParams * n)()
+        for i, q in enumerate(pairs):
+            sp = q.get("spacing", (1.0, 1.0, 1.0))
+            srcs[i] = volume(q["src"], sp, q.get("src_fov"))
+            tgts[i] = volume(q["tgt"], q.get("tgt_spacing", sp), q.get("tgt_fov"))
+            prms[i] = params(q["params"])
+        self.n_particles = [int(q["params"]["n_particles"]) for q in pairs]
+        self.n_iters = [int(q["params"]["n_iters"]) for q in pairs]
+        self.b = C.c_void_p()
+        _check(lib().smc_batch_init(C.byref(self.b), n, C.cast(srcs, C.c_void_p), C.cast(tgts, C.c_void_p),
+                                    C.cast(prms, C.c_void_p), _stream_handle(stream)))
+        self.n = n
+
+    def set_seeds(self, seeds):
+        a = np.ascontiguousarray(seeds, dtype=np.uint64)
+        _check(lib().smc_batch_set_seeds(self.b, _ptr(a)))
+
+    def run(self):
+        _check(lib().smc_batch_run(self.b))
+
+    def pair(self, i):
+        return C.c_void_p(lib().smc_batch_pair(self.b, int(i)))
+
+    def estimate(self, i):
+        return smc_estimate(self.pair(i))
+
+    def particles(self, i):
+        return smc_get_particles(self.pair(i), self.n_particles[i])
+
+    def trace(self, i):
+        return smc_trace(self.pair(i), self.n_iters[i])
+
+    def close(self):
+        if self.b:
+            lib().smc_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

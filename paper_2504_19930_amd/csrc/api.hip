@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,6 +19,10 @@ using namespace smc;
 namespace {
 
 thread_local std::string g_err;
+
+// Launch defaults (see smc_set_tuning).
+constexpr int kDefaultLayout = kLayoutRaw;
+constexpr int kDefaultPT = 8;
 
 smc_status fail(smc_status st, const char *fmt, ...) {
     char buf[512];
@@ -104,6 +109,8 @@ struct smc_ctx {
     int32_t sn[3] = {0, 0, 0}, tn[3] = {0, 0, 0};
     const uint8_t *src = nullptr, *src_fov = nullptr, *tgt = nullptr, *tgt_fov = nullptr;
     uint8_t *src_prep = nullptr, *tgt_prep = nullptr, *src_ok = nullptr;
+    int layout = kDefaultLayout, pt = kDefaultPT;
+    void *packed[4] = {nullptr, nullptr, nullptr, nullptr};
     FilterState f{};
     uint32_t k_done = 0;
     smc_status sticky = SMC_OK;
@@ -146,6 +153,9 @@ struct smc_ctx {
             L.tgt = tgt;
             L.tgt_fov = tgt_fov;
         }
+        L.layout = mode == kModeImageTrilinear ? layout : kLayoutRaw;
+        L.src_packed = mode == kModeImageTrilinear ? packed[L.layout] : nullptr;
+        L.pt = pt;
         L.words = words;
         L.sums = sums;
         for (int d = 0; d < 3; ++d) {
@@ -287,6 +297,13 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
         } else {
             c->src_ok = const_cast<uint8_t *>(src->fov);
         }
+    }
+
+    if (c->mode == kModeImageTrilinear && c->layout != kLayoutRaw) {
+        if ((st = c->alloc((uint8_t **)&c->packed[c->layout], vs * packed_bytes_per_voxel(c->layout))) != SMC_OK)
+            return bail(st);
+        if (launch_pack_source(src->data, c->sn, c->layout, c->packed[c->layout], c->stream) != hipSuccess)
+            return bail(fail(SMC_EDEVICE, "source packing launch failed"));
     }
 
     // exact per-volume sums -> statistics
@@ -526,6 +543,33 @@ smc_status smc_set_state(smc_ctx *c, const void *buf, size_t len) {
     return SMC_OK;
 }
 
+smc_status smc_set_tuning(smc_ctx *c, int32_t layout, int32_t pt) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (layout > kLayoutOct) return fail(SMC_EINVAL, "unknown layout %d", layout);
+    if (pt >= 0 && !score_pt_supported(pt)) return fail(SMC_EINVAL, "particles_per_group must be 4, 8 or 16");
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    if (layout >= 0) {
+        if (c->mode == kModeImageTrilinear && layout != kLayoutRaw && !c->packed[layout]) {
+            const int64_t vs = (int64_t)c->sn[0] * c->sn[1] * c->sn[2];
+            if ((st = c->alloc((uint8_t **)&c->packed[layout], vs * packed_bytes_per_voxel(layout))) != SMC_OK)
+                return st;
+            HIP_TRY(launch_pack_source(c->src, c->sn, layout, c->packed[layout], c->stream));
+        }
+        c->layout = layout;
+    }
+    if (pt >= 0) c->pt = pt;
+    return SMC_OK;
+}
+
+smc_status smc_get_tuning(smc_ctx *c, int32_t *layout, int32_t *pt) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (layout) *layout = c->layout;
+    if (pt) *pt = c->pt;
+    return SMC_OK;
+}
+
 smc_status smc_profile(smc_ctx *c, int32_t enable) {
     if (!c) return fail(SMC_EINVAL, "ctx is NULL");
     c->profiling = enable != 0;
@@ -599,6 +643,249 @@ smc_status warp_apply(const smc_volume *src, const double mat3x4[12], int32_t in
                                      src_frame_stride, dst_frame_stride, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(SMC_EDEVICE, "warp_apply launch failed: %s", hipGetErrorString(e));
     return SMC_OK;
+}
+
+}  // extern "C"
+
+// ===================================================================== batches
+
+struct smc_batch {
+    hipStream_t stream = nullptr;
+    std::vector<smc_ctx *> pairs;
+    std::vector<FilterState> states;
+    FilterState *states_dev = nullptr;
+    uint32_t kmax_all = 0, max_threads = 0;
+    struct Class {
+        BatchPlan plan{};
+        std::vector<uint32_t> members;
+        void *args = nullptr;
+        uint32_t *offs = nullptr, *kmax = nullptr, *lists = nullptr;
+    } cls[2];  // 0 masks, 1 trilinear images (other modes run per pair)
+    std::vector<uint32_t> singles;  // pairs outside the two classes
+    std::vector<void *> allocs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipStream_t caller = nullptr;
+
+    template <typename T>
+    smc_status alloc(T **out, size_t count) {
+        void *ptr = nullptr;
+        if (hipMalloc(&ptr, count * sizeof(T) > 0 ? count * sizeof(T) : 1) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SMC_ENOMEM, "hipMalloc failed in smc_batch_init");
+        }
+        allocs.push_back(ptr);
+        *out = static_cast<T *>(ptr);
+        return SMC_OK;
+    }
+};
+
+namespace {
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    return cus;
+}
+
+// Work list of one class: items of each pair, pairs assigned to the eight
+// XCD lists greedily by work (largest first) so the lists stay balanced.
+smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode) {
+    const uint32_t n = (uint32_t)C.members.size();
+    if (n == 0) return SMC_OK;
+    const size_t ab = score_args_bytes();
+    std::vector<uint8_t> args(ab * n);
+    std::vector<uint32_t> offs(n + 1, 0), kmax(n);
+    std::vector<double> work(n);
+    int pt = 8, layout = kLayoutRaw;
+    for (uint32_t q = 0; q < n; ++q) {
+        smc_ctx *c = b->pairs[C.members[q]];
+        const ScoreLaunch L = c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1);
+        pt = L.pt;
+        layout = L.layout;
+        score_args(L, args.data() + ab * q);
+        const uint32_t items = score_items(L);
+        offs[q + 1] = offs[q] + items;
+        kmax[q] = c->f.n_iters;
+        work[q] = (double)items * (double)c->tn[2];
+    }
+    std::vector<uint32_t> order(n);
+    for (uint32_t q = 0; q < n; ++q) order[q] = q;
+    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t c) { return work[a] > work[c]; });
+    std::vector<std::vector<uint32_t>> lists(8);
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t q : order) {
+        int x = 0;
+        for (int y = 1; y < 8; ++y)
+            if (load[y] < load[x]) x = y;
+        load[x] += work[q];
+        for (uint32_t g = offs[q]; g < offs[q + 1]; ++g) lists[x].push_back(g);
+    }
+    std::vector<uint32_t> flat;
+    C.plan.list_off[0] = 0;
+    for (int x = 0; x < 8; ++x) {
+        flat.insert(flat.end(), lists[x].begin(), lists[x].end());
+        C.plan.list_off[x + 1] = (uint32_t)flat.size();
+    }
+    smc_status st;
+    if ((st = b->alloc((uint8_t **)&C.args, args.size())) != SMC_OK || (st = b->alloc(&C.offs, n + 1)) != SMC_OK ||
+        (st = b->alloc(&C.kmax, n)) != SMC_OK || (st = b->alloc(&C.lists, flat.size())) != SMC_OK)
+        return st;
+    HIP_TRY(hipMemcpy(C.args, args.data(), args.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(C.offs, offs.data(), 4 * (n + 1), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(C.kmax, kmax.data(), 4 * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(C.lists, flat.data(), 4 * flat.size(), hipMemcpyHostToDevice));
+    C.plan.mode = mode;
+    C.plan.layout = layout;
+    C.plan.pt = pt;
+    C.plan.pairs = C.args;
+    C.plan.offs = C.offs;
+    C.plan.kmax = C.kmax;
+    C.plan.lists = C.lists;
+    C.plan.n_pairs = n;
+    // persistent grid: a few workgroups per CU, a multiple of the 8 XCDs
+    const uint32_t per_cu = mode == kModeMask ? 6 : 4;
+    C.plan.grid = 8 * (((uint32_t)device_cus() * per_cu + 7) / 8);
+    return SMC_OK;
+}
+
+// The whole batched run, recorded on b->stream (captured into the graph).
+smc_status record_run(smc_batch *b) {
+    HIP_TRY(launch_init_batch(b->states_dev, (uint32_t)b->pairs.size(), b->max_threads, b->stream));
+    for (smc_ctx *c : b->pairs) HIP_TRY(launch_fill_u64(c->f.sums, 6ull * (c->f.n + 1), b->stream));
+    for (uint32_t k = 1; k <= b->kmax_all; ++k) {
+        for (int q = 0; q < 2; ++q) HIP_TRY(launch_batch_score(b->cls[q].plan, k, b->stream));
+        for (uint32_t i : b->singles) {
+            smc_ctx *c = b->pairs[i];
+            if (k <= c->f.n_iters)
+                HIP_TRY(launch_score(c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1), b->stream));
+        }
+        HIP_TRY(launch_filter_batch(b->states_dev, (uint32_t)b->pairs.size(), k, b->stream));
+        for (smc_ctx *c : b->pairs)
+            if (c->f.n_iters == k) {
+                HIP_TRY(launch_score(c->score_launch(c->f.words, c->f.sums, c->f.n, 1), b->stream));
+                HIP_TRY(launch_ghost_final(c->f, b->stream));
+            }
+    }
+    return SMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+smc_status smc_batch_init(smc_batch **out, uint32_t n_pairs, const smc_volume *src, const smc_volume *tgt,
+                          const smc_params *p, void *hip_stream) {
+    g_err.clear();
+    if (!out) return fail(SMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_pairs < 1 || n_pairs > 4096) return fail(SMC_EINVAL, "n_pairs must be in 1..4096");
+    if (!src || !tgt || !p) return fail(SMC_EINVAL, "src, tgt and p must not be NULL");
+    smc_batch *b = new (std::nothrow) smc_batch();
+    if (!b) return fail(SMC_ENOMEM, "host allocation failed");
+    b->caller = (hipStream_t)hip_stream;
+    auto bail = [&](smc_status st) {
+        std::string msg = g_err;
+        smc_batch_destroy(b);
+        g_err = msg;
+        return st;
+    };
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(SMC_EDEVICE, "stream / event creation failed"));
+    smc_status st;
+    for (uint32_t i = 0; i < n_pairs; ++i) {
+        smc_ctx *c = nullptr;
+        if ((st = smc_init(&c, &src[i], &tgt[i], &p[i], b->stream)) != SMC_OK) {
+            std::string msg = g_err;
+            return bail(fail(st, "pair %u: %s", i, msg.c_str()));
+        }
+        b->pairs.push_back(c);
+        b->states.push_back(c->f);
+        b->kmax_all = std::max(b->kmax_all, c->f.n_iters);
+        b->max_threads = std::max(b->max_threads, std::max(c->f.n, c->f.n_iters + 1));
+        if (c->mode == kModeMask) b->cls[0].members.push_back(i);
+        else if (c->mode == kModeImageTrilinear) b->cls[1].members.push_back(i);
+        else b->singles.push_back(i);
+    }
+    // one layout / particles-per-group for all trilinear pairs: the first pair's
+    for (uint32_t q = 1; q < b->cls[1].members.size(); ++q) {
+        smc_ctx *c0 = b->pairs[b->cls[1].members[0]], *c = b->pairs[b->cls[1].members[q]];
+        if ((st = smc_set_tuning(c, c0->layout, c0->pt)) != SMC_OK) return bail(st);
+    }
+    if ((st = b->alloc(&b->states_dev, n_pairs)) != SMC_OK) return bail(st);
+    if (hipMemcpy(b->states_dev, b->states.data(), sizeof(FilterState) * n_pairs, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(SMC_EDEVICE, "upload of filter states failed"));
+    if ((st = plan_class(b, b->cls[0], kModeMask)) != SMC_OK) return bail(st);
+    if ((st = plan_class(b, b->cls[1], kModeImageTrilinear)) != SMC_OK) return bail(st);
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return bail(fail(SMC_EDEVICE, "batch preparation failed"));
+    *out = b;
+    return SMC_OK;
+}
+
+smc_status smc_batch_set_seeds(smc_batch *b, const uint64_t *seeds) {
+    if (!b) return fail(SMC_EINVAL, "batch is NULL");
+    if (!seeds) return SMC_OK;
+    for (size_t i = 0; i < b->pairs.size(); ++i) {
+        b->states[i].seed = seeds[i];
+        b->pairs[i]->f.seed = seeds[i];
+        b->pairs[i]->p.seed = seeds[i];
+    }
+    // ordered on the batch stream, so it cannot overtake a running replay
+    HIP_TRY(hipMemcpyAsync(b->states_dev, b->states.data(), sizeof(FilterState) * b->states.size(),
+                           hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return SMC_OK;
+}
+
+smc_status smc_batch_run(smc_batch *b) {
+    if (!b) return fail(SMC_EINVAL, "batch is NULL");
+    for (smc_ctx *c : b->pairs) {
+        smc_status st = c->check_sticky();
+        if (st != SMC_OK) return st;
+    }
+    if (!b->exec) {
+        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        smc_status st = record_run(b);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (st != SMC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(SMC_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        b->graph = g;
+        HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    HIP_TRY(hipEventRecord(b->ev_in, b->caller));
+    HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    HIP_TRY(hipEventRecord(b->ev_out, b->stream));
+    HIP_TRY(hipStreamWaitEvent(b->caller, b->ev_out, 0));
+    for (smc_ctx *c : b->pairs) c->k_done = c->f.n_iters;
+    return SMC_OK;
+}
+
+smc_ctx *smc_batch_pair(smc_batch *b, uint32_t i) {
+    if (!b || i >= b->pairs.size()) return nullptr;
+    return b->pairs[i];
+}
+
+void smc_batch_destroy(smc_batch *b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (smc_ctx *c : b->pairs) smc_destroy(c);
+    for (void *ptr : b->allocs) (void)hipFree(ptr);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
 }
 
 }  // extern "C"

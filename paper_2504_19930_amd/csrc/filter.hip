@@ -40,8 +40,7 @@ __global__ __launch_bounds__(256) void k_words(const double *x, uint32_t n, Geom
 }
 
 // Prior: x_i = x0 + L (2u - 1), u from Philox (tag 0, three blocks).
-__global__ __launch_bounds__(256) void k_init(const FilterState f) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void init_body(const FilterState &f, uint32_t i, uint32_t stride) {
     if (i < f.n) {
         double p[6];
         for (uint32_t b = 0; b < 3; ++b) {
@@ -63,7 +62,7 @@ __global__ __launch_bounds__(256) void k_init(const FilterState f) {
         f.flags[0] = 0;
     }
     const uint32_t nt = f.n_iters + 1;
-    for (uint32_t q = i; q < nt; q += gridDim.x * blockDim.x) {
+    for (uint32_t q = i; q < nt; q += stride) {
         f.trace_score[q] = __builtin_nan("");
         if (q < f.n_iters) {
             f.trace_ess[q] = __builtin_nan("");
@@ -72,12 +71,22 @@ __global__ __launch_bounds__(256) void k_init(const FilterState f) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_init(const FilterState f) {
+    init_body(f, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_init_batch(const FilterState *fs) {
+    const FilterState &f = fs[blockIdx.y];
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < f.n || i < f.n_iters + 1) init_body(f, i, gridDim.x * blockDim.x);
+}
+
 __device__ __forceinline__ bool pointer_passed(unsigned long long c, unsigned __int128 scale,
                                                unsigned __int128 rhs) {
     return (unsigned __int128)c * scale > rhs;
 }
 
-__global__ __launch_bounds__(kFT) void k_filter(const FilterState f, const uint32_t k) {
+__device__ __forceinline__ void filter_body(const FilterState &f, const uint32_t k) {
     __shared__ double red[kFW][8];
     __shared__ double bcast[8];
     __shared__ unsigned long long scan[kFT];
@@ -215,6 +224,13 @@ __global__ __launch_bounds__(kFT) void k_filter(const FilterState f, const uint3
     for (uint32_t q = tid; q < 6 * (n + 1); q += kFT) f.sums[q] = 0ull;
 }
 
+__global__ __launch_bounds__(kFT) void k_filter(const FilterState f, const uint32_t k) { filter_body(f, k); }
+
+__global__ __launch_bounds__(kFT) void k_filter_batch(const FilterState *fs, const uint32_t k) {
+    const FilterState &f = fs[blockIdx.x];
+    if (k <= f.n_iters) filter_body(f, k);
+}
+
 __global__ void k_ghost_final(const FilterState f) {
     int64_t m[6];
     for (int q = 0; q < 6; ++q) m[q] = (int64_t)f.sums[6 * (size_t)f.n + q];
@@ -245,6 +261,16 @@ hipError_t launch_init_particles(const FilterState &f, hipStream_t s) {
 
 hipError_t launch_filter(const FilterState &f, uint32_t k, hipStream_t s) {
     hipLaunchKernelGGL(k_filter, dim3(1), dim3(kFT), 0, s, f, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_batch(const FilterState *fs, uint32_t n_pairs, uint32_t max_threads, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_batch, dim3((max_threads + 255) / 256, n_pairs), dim3(256), 0, s, fs);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_batch(const FilterState *fs, uint32_t n_pairs, uint32_t k, hipStream_t s) {
+    hipLaunchKernelGGL(k_filter_batch, dim3(n_pairs), dim3(kFT), 0, s, fs, k);
     return hipGetLastError();
 }
 

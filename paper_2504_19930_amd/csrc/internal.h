@@ -12,9 +12,16 @@ namespace smc {
 // accumulated (atomically, exactly) into sums[6 * p].
 enum ScoreMode : int { kModeMask = 0, kModeImageTrilinear = 1, kModeImageNearest = 2 };
 
+// Source layouts for trilinear sampling (see score.hip): bytes per voxel
+// 1, 2, 4, 8; eight, four, two or one gathers per sample.
+enum SourceLayout : int { kLayoutRaw = 0, kLayoutPairX = 1, kLayoutQuadXY = 2, kLayoutOct = 3 };
+
 struct ScoreLaunch {
     int mode;
     const uint8_t *src;       // mask: prepared bits; image: intensities
+    const void *src_packed;   // trilinear: source in `layout` (nullptr = raw bytes)
+    int layout;               // SourceLayout
+    int pt;                   // particles per workgroup: 4, 8 or 16
     const uint8_t *src_ok;    // image: corner-valid bytes (source FOV) or nullptr
     const uint8_t *tgt;       // mask: prepared bits; image: intensities
     const uint8_t *tgt_fov;   // image: target FOV or nullptr
@@ -26,6 +33,27 @@ struct ScoreLaunch {
 
 hipError_t launch_score(const ScoreLaunch &L, hipStream_t s);
 void score_grid(const ScoreLaunch &L, dim3 *grid, dim3 *block);
+bool score_pt_supported(int pt);
+// Pack a source volume into `layout` (edge corners repeat the last voxel).
+hipError_t launch_pack_source(const uint8_t *vol, const int32_t n[3], int layout, void *out, hipStream_t s);
+size_t packed_bytes_per_voxel(int layout);
+
+// Batched warp-and-score: one persistent launch over the work items of many
+// pairs of one class (masks, or trilinear images in one layout).
+struct BatchPlan {
+    int mode, layout, pt;
+    const void *pairs;        // device array of per-pair kernel arguments (score_args)
+    const uint32_t *offs;     // n_pairs + 1 item offsets
+    const uint32_t *kmax;     // iterations per pair
+    const uint32_t *lists;    // item ids grouped by XCD
+    uint32_t list_off[9];
+    uint32_t n_pairs;
+    uint32_t grid;            // persistent workgroups
+};
+size_t score_args_bytes();
+uint32_t score_items(const ScoreLaunch &L);
+void score_args(const ScoreLaunch &L, void *out);
+hipError_t launch_batch_score(const BatchPlan &P, uint32_t k, hipStream_t s);
 
 // Preparation of inputs.
 hipError_t launch_prep_mask(const uint8_t *vol, const uint8_t *fov, uint8_t *out, int64_t n, hipStream_t s);
@@ -60,6 +88,9 @@ struct FilterState {
 };
 
 hipError_t launch_init_particles(const FilterState &f, hipStream_t s);
+// Batched filter: one workgroup per pair, states in device memory.
+hipError_t launch_init_batch(const FilterState *states_dev, uint32_t n_pairs, uint32_t max_threads, hipStream_t s);
+hipError_t launch_filter_batch(const FilterState *states_dev, uint32_t n_pairs, uint32_t k, hipStream_t s);
 hipError_t launch_filter(const FilterState &f, uint32_t k, hipStream_t s);
 hipError_t launch_ghost_final(const FilterState &f, hipStream_t s);
 hipError_t launch_words(const double *x, uint32_t n, const Geom &g, bool nearest, float *words, hipStream_t s);

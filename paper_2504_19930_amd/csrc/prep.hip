@@ -66,6 +66,32 @@ __global__ __launch_bounds__(256) void k_volume_sums(const uint8_t *vol, const u
     }
 }
 
+// Trilinear source layouts: per base voxel the corner bytes the kernel needs,
+// with corners past the last voxel repeating it (see score.hip).
+__global__ void k_pack_source(const uint8_t *vol, int32_t nx, int32_t ny, int32_t nz, int layout, void *out) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = (int32_t)(q % nx);
+        const int32_t j = (int32_t)((q / nx) % ny);
+        const int32_t k = (int32_t)(q / ((int64_t)nx * ny));
+        const int64_t dx = i + 1 < nx ? 1 : 0;
+        const int64_t dy = j + 1 < ny ? nx : 0;
+        const int64_t dz = k + 1 < nz ? (int64_t)nx * ny : 0;
+        const uint32_t q0 = (uint32_t)vol[q] | ((uint32_t)vol[q + dx] << 8) | ((uint32_t)vol[q + dy] << 16) |
+                            ((uint32_t)vol[q + dy + dx] << 24);
+        if (layout == kLayoutPairX) {
+            ((uint16_t *)out)[q] = (uint16_t)(q0 & 0xFFFFu);
+        } else if (layout == kLayoutQuadXY) {
+            ((uint32_t *)out)[q] = q0;
+        } else {
+            const int64_t r = q + dz;
+            const uint32_t q1 = (uint32_t)vol[r] | ((uint32_t)vol[r + dx] << 8) | ((uint32_t)vol[r + dy] << 16) |
+                                ((uint32_t)vol[r + dy + dx] << 24);
+            ((uint2 *)out)[q] = make_uint2(q0, q1);
+        }
+    }
+}
+
 unsigned blocks_for(int64_t n) {
     int64_t b = (n + 255) / 256;
     return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
@@ -81,6 +107,22 @@ hipError_t launch_prep_mask(const uint8_t *vol, const uint8_t *fov, uint8_t *out
 hipError_t launch_corner_valid(const uint8_t *fov, uint8_t *out, const int32_t n[3], hipStream_t s) {
     const int64_t tot = (int64_t)n[0] * n[1] * n[2];
     hipLaunchKernelGGL(k_corner_valid, dim3(blocks_for(tot)), dim3(256), 0, s, fov, out, n[0], n[1], n[2]);
+    return hipGetLastError();
+}
+
+size_t packed_bytes_per_voxel(int layout) {
+    switch (layout) {
+    case kLayoutPairX: return 2;
+    case kLayoutQuadXY: return 4;
+    case kLayoutOct: return 8;
+    default: return 1;
+    }
+}
+
+hipError_t launch_pack_source(const uint8_t *vol, const int32_t n[3], int layout, void *out, hipStream_t s) {
+    if (layout == kLayoutRaw) return hipSuccess;
+    const int64_t tot = (int64_t)n[0] * n[1] * n[2];
+    hipLaunchKernelGGL(k_pack_source, dim3(blocks_for(tot)), dim3(256), 0, s, vol, n[0], n[1], n[2], layout, out);
     return hipGetLastError();
 }
 

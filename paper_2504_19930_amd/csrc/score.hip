@@ -14,6 +14,8 @@
 // are reduced across the wave with shuffles, across the four waves in LDS,
 // and land with one 64-bit atomic add per (workgroup, particle, sum).  Integer
 // addition is associative, so the result does not depend on scheduling.
+#include <string.h>
+
 #include "internal.h"
 
 namespace smc {
@@ -27,6 +29,7 @@ constexpr int kZChunkMax = 256;  // keeps every per-thread 32-bit sum below 2^32
 
 struct KArgs {
     const uint8_t *src, *src_ok, *tgt, *tgt_fov;
+    const void *src_packed;
     const float *words;
     unsigned long long *sums;
     int32_t sn0, sn1, sn2, tn0, tn1, tn2;
@@ -53,10 +56,10 @@ struct Tile {
 };
 
 template <int PT>
-__device__ __forceinline__ Tile tile_of(const KArgs &a) {
+__device__ __forceinline__ Tile tile_of(const KArgs &a, uint32_t bx, uint32_t by) {
     Tile t;
     const int tiles = a.tiles_x * a.tiles_y;
-    int b = blockIdx.x;
+    int b = (int)bx;
     const int zc = b / tiles;
     b -= zc * tiles;
     const int ty = b / a.tiles_x;
@@ -66,7 +69,7 @@ __device__ __forceinline__ Tile tile_of(const KArgs &a) {
     t.ok = t.i < a.tn0 && t.j < a.tn1;
     t.k0 = zc * a.zchunk;
     t.k1 = min(t.k0 + a.zchunk, a.tn2);
-    t.pbase = a.p0 + blockIdx.y * PT;
+    t.pbase = a.p0 + by * PT;
     t.npg = min(PT, (int)(a.p0 + a.np - t.pbase));
     return t;
 }
@@ -99,8 +102,8 @@ __device__ __forceinline__ void column_terms(const KArgs &a, const Tile &t, floa
 // Per particle two packed counters: acc1 = n | a << 16, acc2 = b_ov | c << 16
 // (each half counts at most one voxel per z step, and a z-chunk < 2^16).
 template <int PT>
-__global__ __launch_bounds__(kThreads) void k_score_mask(const KArgs a) {
-    const Tile t = tile_of<PT>(a);
+__device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t by) {
+    const Tile t = tile_of<PT>(a, bx, by);
     float mx[PT], my[PT], mz[PT], ax[PT], ay[PT], az[PT];
     column_terms<PT>(a, t, mx, my, mz, ax, ay, az);
     uint32_t acc1[PT], acc2[PT];
@@ -162,28 +165,88 @@ __global__ __launch_bounds__(kThreads) void k_score_mask(const KArgs a) {
 
 // ---------------------------------------------------------------- images
 
+// The eight trilinear corners of base voxel (ix, iy, iz) as floats, read from
+// one of the source layouts (corners beyond the last voxel repeat it; their
+// weight is zero there):
+//   raw    uint8 per voxel, eight byte gathers
+//   pairx  uint16 (v[x], v[x+1]), four gathers
+//   quadxy uint32 (v[x,y], v[x+1,y], v[x,y+1], v[x+1,y+1]), two gathers
+//   oct    uint64 (quad of slice z, quad of slice z+1), one gather
+template <int LAYOUT>
+__device__ __forceinline__ void corners(const void *src, uint32_t base, uint32_t dx, uint32_t dy, uint32_t dz,
+                                        float v[8]) {
+    if (LAYOUT == kLayoutRaw) {
+        const uint8_t *S = (const uint8_t *)src + base;
+        v[0] = (float)S[0];
+        v[1] = (float)S[dx];
+        v[2] = (float)S[dy];
+        v[3] = (float)S[dy + dx];
+        v[4] = (float)S[dz];
+        v[5] = (float)S[dz + dx];
+        v[6] = (float)S[dz + dy];
+        v[7] = (float)S[dz + dy + dx];
+    } else if (LAYOUT == kLayoutPairX) {
+        const uint16_t *S = (const uint16_t *)src + base;
+        const uint32_t a = S[0], b = S[dy], c = S[dz], d = S[dz + dy];
+        v[0] = (float)(a & 0xFFu);
+        v[1] = (float)(a >> 8);
+        v[2] = (float)(b & 0xFFu);
+        v[3] = (float)(b >> 8);
+        v[4] = (float)(c & 0xFFu);
+        v[5] = (float)(c >> 8);
+        v[6] = (float)(d & 0xFFu);
+        v[7] = (float)(d >> 8);
+    } else {
+        uint32_t lo, hi;
+        if (LAYOUT == kLayoutQuadXY) {
+            const uint32_t *S = (const uint32_t *)src + base;
+            lo = S[0];
+            hi = S[dz];
+        } else {
+            const uint2 w = ((const uint2 *)src)[base];
+            lo = w.x;
+            hi = w.y;
+        }
+        v[0] = (float)(lo & 0xFFu);
+        v[1] = (float)((lo >> 8) & 0xFFu);
+        v[2] = (float)((lo >> 16) & 0xFFu);
+        v[3] = (float)(lo >> 24);
+        v[4] = (float)(hi & 0xFFu);
+        v[5] = (float)((hi >> 8) & 0xFFu);
+        v[6] = (float)((hi >> 16) & 0xFFu);
+        v[7] = (float)(hi >> 24);
+    }
+}
+
+struct Sums6 {
+    uint32_t n, s, t, tt, st;
+    unsigned long long ss;
+};
+
 // Sums per particle over the overlap: n, s, t, s^2, t^2, s t with s the
 // sampled source value in units of 1/256 (exact: s_fx = floor(256 s + 0.5)).
-template <int PT, bool TRI, bool SOK, bool TFOV>
-__global__ __launch_bounds__(kThreads) void k_score_image(const KArgs a) {
-    const Tile t = tile_of<PT>(a);
+// TRI: trilinear (inside iff 0 <= u <= n - 1 and the eight corners in the
+// source FOV); otherwise nearest (the words carry the +0.5 shift).
+template <int PT, int LAYOUT, bool TRI, bool SOK>
+__device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t by) {
+    const Tile t = tile_of<PT>(a, bx, by);
     float mx[PT], my[PT], mz[PT], ax[PT], ay[PT], az[PT];
     column_terms<PT>(a, t, mx, my, mz, ax, ay, az);
-    uint32_t cn[PT], cs[PT], ct[PT], ctt[PT], cst[PT];
-    unsigned long long css[PT];
+    Sums6 acc[PT];
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
-        cn[p] = cs[p] = ct[p] = ctt[p] = cst[p] = 0u;
-        css[p] = 0ull;
+        acc[p].n = acc[p].s = acc[p].t = acc[p].tt = acc[p].st = 0u;
+        acc[p].ss = 0ull;
     }
     if (t.ok) {
         const size_t plane = (size_t)a.tn0 * (size_t)a.tn1;
         const size_t tofs0 = (size_t)t.i + (size_t)a.tn0 * (size_t)t.j;
         const uint32_t sn0 = (uint32_t)a.sn0, sn01 = (uint32_t)a.sn0 * (uint32_t)a.sn1;
         const float ex = (float)(a.sn0 - 1), ey = (float)(a.sn1 - 1), ez = (float)(a.sn2 - 1);
+        const bool tfov = a.tgt_fov != nullptr;
         for (int k = t.k0; k < t.k1; ++k) {
             const size_t tofs = tofs0 + plane * (size_t)k;
-            if (TFOV && a.tgt_fov[tofs] == 0) continue;
+            if (tfov && a.tgt_fov[tofs] == 0) continue;
             const uint32_t tv = a.tgt[tofs];
             const uint32_t tv2 = tv * tv;
             const float fk = (float)k;
@@ -205,19 +268,16 @@ __global__ __launch_bounds__(kThreads) void k_score_image(const KArgs a) {
                         const uint32_t dx = ix < (uint32_t)(a.sn0 - 1) ? 1u : 0u;
                         const uint32_t dy = iy < (uint32_t)(a.sn1 - 1) ? sn0 : 0u;
                         const uint32_t dz = iz < (uint32_t)(a.sn2 - 1) ? sn01 : 0u;
-                        const uint8_t *S = a.src + base;
-                        const float v000 = (float)S[0], v100 = (float)S[dx];
-                        const float v010 = (float)S[dy], v110 = (float)S[dy + dx];
-                        const float v001 = (float)S[dz], v101 = (float)S[dz + dx];
-                        const float v011 = (float)S[dz + dy], v111 = (float)S[dz + dy + dx];
-                        const float x00 = fmaf(fx, v100 - v000, v000);
-                        const float x10 = fmaf(fx, v110 - v010, v010);
-                        const float x01 = fmaf(fx, v101 - v001, v001);
-                        const float x11 = fmaf(fx, v111 - v011, v011);
+                        float v[8];
+                        corners<LAYOUT>(a.src_packed, base, dx, dy, dz, v);
+                        const float x00 = fmaf(fx, v[1] - v[0], v[0]);
+                        const float x10 = fmaf(fx, v[3] - v[2], v[2]);
+                        const float x01 = fmaf(fx, v[5] - v[4], v[4]);
+                        const float x11 = fmaf(fx, v[7] - v[6], v[6]);
                         const float y0 = fmaf(fy, x10 - x00, x00);
                         const float y1 = fmaf(fy, x11 - x01, x01);
-                        const float s = fmaf(fz, y1 - y0, y0);
-                        sfx = (uint32_t)(s * 256.0f + 0.5f);
+                        const float sv = fmaf(fz, y1 - y0, y0);
+                        sfx = (uint32_t)(sv * 256.0f + 0.5f);
                     } else {
                         const int ix = (int)floorf(ux), iy = (int)floorf(uy), iz = (int)floorf(uz);
                         if (!((uint32_t)ix < (uint32_t)a.sn0 && (uint32_t)iy < (uint32_t)a.sn1 &&
@@ -227,12 +287,12 @@ __global__ __launch_bounds__(kThreads) void k_score_image(const KArgs a) {
                         if (SOK && a.src_ok[m] == 0) continue;
                         sfx = (uint32_t)a.src[m] << 8;
                     }
-                    cn[p] += 1u;
-                    cs[p] += sfx;
-                    ct[p] += tv;
-                    css[p] += (unsigned long long)sfx * sfx;
-                    ctt[p] += tv2;
-                    cst[p] += sfx * tv;
+                    acc[p].n += 1u;
+                    acc[p].s += sfx;
+                    acc[p].t += tv;
+                    acc[p].ss += (unsigned long long)sfx * sfx;
+                    acc[p].tt += tv2;
+                    acc[p].st += sfx * tv;
                 }
             }
         }
@@ -241,12 +301,12 @@ __global__ __launch_bounds__(kThreads) void k_score_image(const KArgs a) {
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
-        const uint32_t n = wave_sum(cn[p]);
-        const uint32_t s1 = wave_sum(cs[p]);
-        const uint32_t t1 = wave_sum(ct[p]);
-        const unsigned long long s2 = wave_sum(css[p]);
-        const uint32_t t2 = wave_sum(ctt[p]);
-        const unsigned long long st = wave_sum((unsigned long long)cst[p]);
+        const uint32_t n = wave_sum(acc[p].n);
+        const uint32_t s1 = wave_sum(acc[p].s);
+        const uint32_t t1 = wave_sum(acc[p].t);
+        const unsigned long long s2 = wave_sum(acc[p].ss);
+        const uint32_t t2 = wave_sum(acc[p].tt);
+        const unsigned long long st = wave_sum((unsigned long long)acc[p].st);
         if (lane == 0) {
             red[wave][p][0] = n;
             red[wave][p][1] = s1;
@@ -268,11 +328,69 @@ __global__ __launch_bounds__(kThreads) void k_score_image(const KArgs a) {
     }
 }
 
-constexpr int kPT = 8;
+template <int PT>
+__global__ __launch_bounds__(kThreads) void k_score_mask(const KArgs a) {
+    mask_body<PT>(a, blockIdx.x, blockIdx.y);
+}
 
-KArgs make_args(const ScoreLaunch &L, int *nz_chunks) {
+template <int PT, int LAYOUT, bool TRI, bool SOK>
+__global__ __launch_bounds__(kThreads) void k_score_image(const KArgs a) {
+    image_body<PT, LAYOUT, TRI, SOK>(a, blockIdx.x, blockIdx.y);
+}
+
+// ---------------------------------------------------------------- batches
+
+// Persistent warp-and-score over the work items of many pairs.  Item g of
+// pair d (offs[d] <= g < offs[d + 1]) is tile g - offs[d] mod ntiles(d) and
+// particle group (g - offs[d]) / ntiles(d).  Work lists are partitioned by
+// XCD: workgroup b serves list b % 8 (the dispatcher hands workgroups to the
+// eight XCDs round robin), so each pair's items stay on one XCD's L2.
+struct BatchArgs {
+    const KArgs *pairs;
+    const uint32_t *offs;      // n_pairs + 1 item offsets
+    const uint32_t *kmax;      // iterations of each pair
+    const uint32_t *lists;     // items, grouped by XCD
+    uint32_t list_off[9];      // list x = lists[list_off[x] .. list_off[x + 1])
+    uint32_t n_pairs;
+    uint32_t k;                // iteration being scored (pairs with kmax < k are done)
+};
+
+__device__ __forceinline__ uint32_t pair_of(const uint32_t *offs, uint32_t n, uint32_t g) {
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (offs[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int PT, int MODE, int LAYOUT>
+__global__ __launch_bounds__(kThreads) void k_batch_score(const BatchArgs b) {
+    const uint32_t x = blockIdx.x % 8, per = gridDim.x / 8 + ((blockIdx.x % 8) < gridDim.x % 8 ? 1u : 0u);
+    const uint32_t begin = b.list_off[x], end = b.list_off[x + 1];
+    for (uint32_t q = begin + blockIdx.x / 8; q < end; q += per) {
+        const uint32_t g = b.lists[q];
+        const uint32_t d = pair_of(b.offs, b.n_pairs, g);
+        if (b.kmax[d] < b.k) continue;
+        const KArgs &a = b.pairs[d];
+        const uint32_t local = g - b.offs[d];
+        const uint32_t nbx = (uint32_t)(a.tiles_x * a.tiles_y) * (uint32_t)((a.tn2 + a.zchunk - 1) / a.zchunk);
+        if (MODE == kModeMask) {
+            mask_body<PT>(a, local % nbx, local / nbx);
+        } else if (a.src_ok) {
+            image_body<PT, LAYOUT, true, true>(a, local % nbx, local / nbx);
+        } else {
+            image_body<PT, LAYOUT, true, false>(a, local % nbx, local / nbx);
+        }
+        __syncthreads();
+    }
+}
+
+KArgs make_args(const ScoreLaunch &L, int pt, int *nz_chunks) {
     KArgs a;
     a.src = L.src;
+    a.src_packed = L.src_packed ? L.src_packed : (const void *)L.src;
     a.src_ok = L.src_ok;
     a.tgt = L.tgt;
     a.tgt_fov = L.tgt_fov;
@@ -291,39 +409,105 @@ KArgs make_args(const ScoreLaunch &L, int *nz_chunks) {
     const int chunks = (L.tn[2] + kZChunkMax - 1) / kZChunkMax;
     a.zchunk = (L.tn[2] + chunks - 1) / chunks;
     *nz_chunks = chunks;
+    (void)pt;
     return a;
+}
+
+typedef void (*ScoreKernel)(const KArgs);
+
+template <int PT, int LAYOUT>
+ScoreKernel pick_tri(bool sok) {
+    return sok ? k_score_image<PT, LAYOUT, true, true> : k_score_image<PT, LAYOUT, true, false>;
+}
+
+template <int PT>
+ScoreKernel pick_tri_layout(int layout, bool sok) {
+    switch (layout) {
+    case kLayoutPairX: return pick_tri<PT, kLayoutPairX>(sok);
+    case kLayoutQuadXY: return pick_tri<PT, kLayoutQuadXY>(sok);
+    case kLayoutOct: return pick_tri<PT, kLayoutOct>(sok);
+    default: return pick_tri<PT, kLayoutRaw>(sok);
+    }
+}
+
+template <int PT>
+ScoreKernel pick(const ScoreLaunch &L) {
+    if (L.mode == kModeMask) return k_score_mask<PT>;
+    const bool sok = L.src_ok != nullptr;
+    if (L.mode == kModeImageNearest)
+        return sok ? k_score_image<PT, kLayoutRaw, false, true> : k_score_image<PT, kLayoutRaw, false, false>;
+    return pick_tri_layout<PT>(L.layout, sok);
 }
 
 }  // namespace
 
+bool score_pt_supported(int pt) { return pt == 4 || pt == 8 || pt == 16; }
+
+size_t score_args_bytes() { return sizeof(KArgs); }
+
+uint32_t score_items(const ScoreLaunch &L) {
+    dim3 grid, block;
+    score_grid(L, &grid, &block);
+    return grid.x * grid.y;
+}
+
+void score_args(const ScoreLaunch &L, void *out) {
+    int chunks;
+    const KArgs a = make_args(L, score_pt_supported(L.pt) ? L.pt : 8, &chunks);
+    memcpy(out, &a, sizeof a);
+}
+
+namespace {
+template <int PT>
+ScoreKernel pick_batch(int mode, int layout) {
+    typedef void (*BK)(const BatchArgs);
+    BK k;
+    if (mode == kModeMask) k = k_batch_score<PT, kModeMask, kLayoutRaw>;
+    else if (layout == kLayoutPairX) k = k_batch_score<PT, kModeImageTrilinear, kLayoutPairX>;
+    else if (layout == kLayoutQuadXY) k = k_batch_score<PT, kModeImageTrilinear, kLayoutQuadXY>;
+    else if (layout == kLayoutOct) k = k_batch_score<PT, kModeImageTrilinear, kLayoutOct>;
+    else k = k_batch_score<PT, kModeImageTrilinear, kLayoutRaw>;
+    return reinterpret_cast<ScoreKernel>(k);
+}
+}  // namespace
+
+hipError_t launch_batch_score(const BatchPlan &P, uint32_t k, hipStream_t s) {
+    if (P.n_pairs == 0) return hipSuccess;
+    BatchArgs b;
+    b.pairs = (const KArgs *)P.pairs;
+    b.offs = P.offs;
+    b.kmax = P.kmax;
+    b.lists = P.lists;
+    for (int x = 0; x < 9; ++x) b.list_off[x] = P.list_off[x];
+    b.n_pairs = P.n_pairs;
+    b.k = k;
+    typedef void (*BK)(const BatchArgs);
+    BK kern;
+    const int pt = score_pt_supported(P.pt) ? P.pt : 8;
+    if (pt == 4) kern = reinterpret_cast<BK>(pick_batch<4>(P.mode, P.layout));
+    else if (pt == 16) kern = reinterpret_cast<BK>(pick_batch<16>(P.mode, P.layout));
+    else kern = reinterpret_cast<BK>(pick_batch<8>(P.mode, P.layout));
+    hipLaunchKernelGGL(kern, dim3(P.grid), dim3(kThreads), 0, s, b);
+    return hipGetLastError();
+}
+
 void score_grid(const ScoreLaunch &L, dim3 *grid, dim3 *block) {
     int chunks;
-    const KArgs a = make_args(L, &chunks);
-    *grid = dim3((unsigned)(a.tiles_x * a.tiles_y * chunks), (L.np + kPT - 1) / kPT, 1);
+    const int pt = score_pt_supported(L.pt) ? L.pt : 8;
+    const KArgs a = make_args(L, pt, &chunks);
+    *grid = dim3((unsigned)(a.tiles_x * a.tiles_y * chunks), (L.np + pt - 1) / pt, 1);
     *block = dim3(kThreads, 1, 1);
 }
 
 hipError_t launch_score(const ScoreLaunch &L, hipStream_t s) {
     if (L.np == 0) return hipSuccess;
     int chunks;
-    const KArgs a = make_args(L, &chunks);
+    const int pt = score_pt_supported(L.pt) ? L.pt : 8;
+    const KArgs a = make_args(L, pt, &chunks);
     dim3 grid, block;
     score_grid(L, &grid, &block);
-    if (L.mode == kModeMask) {
-        hipLaunchKernelGGL(k_score_mask<kPT>, grid, block, 0, s, a);
-    } else {
-        const bool tri = L.mode == kModeImageTrilinear;
-        const bool sok = L.src_ok != nullptr, tfov = L.tgt_fov != nullptr;
-#define SMC_IMG(T, A, B) hipLaunchKernelGGL((k_score_image<kPT, T, A, B>), grid, block, 0, s, a)
-        if (tri) {
-            if (sok) { if (tfov) SMC_IMG(true, true, true); else SMC_IMG(true, true, false); }
-            else { if (tfov) SMC_IMG(true, false, true); else SMC_IMG(true, false, false); }
-        } else {
-            if (sok) { if (tfov) SMC_IMG(false, true, true); else SMC_IMG(false, true, false); }
-            else { if (tfov) SMC_IMG(false, false, true); else SMC_IMG(false, false, false); }
-        }
-#undef SMC_IMG
-    }
+    ScoreKernel k = pt == 4 ? pick<4>(L) : (pt == 16 ? pick<16>(L) : pick<8>(L));
+    hipLaunchKernelGGL(k, grid, block, 0, s, a);
     return hipGetLastError();
 }
 

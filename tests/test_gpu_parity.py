@@ -271,3 +271,67 @@ def test_lv224_full_size_sampled_and_warp_all_frames(smc, orc):
         o = out.cpu().numpy()
         for f in (0, len(frames) - 1):
             assert np.array_equal(o[f], orc.warp_apply(frames[f], M, interp == "trilinear", shape))
+
+
+def test_tuning_invariance(smc, orc):
+    """Every source layout and particles-per-group setting gives the same sums
+    (and they equal the oracle's)."""
+    pair = synth.speckle_pair(side=37, seed=17, trans=3.0)
+    prm = config.default_params("ncc", 41, 3, 20.0, 3.0)
+    r = _reg(smc, pair, prm, src_fov=pair["src_fov"])
+    x = np.vstack([np.zeros(6), _random_states(40, 20, 3, 8)])
+    want = _oracle_sums(orc, orc.Volume(pair["src"], fov=pair["src_fov"]), orc.Volume(pair["tgt"]), x, "trilinear")
+    for layout in ("raw", "pairx", "quadxy", "oct"):
+        for pt in (4, 8, 16):
+            r.tune(layout, pt)
+            assert r.tuning() == dict(layout=smc.LAYOUTS[layout], particles_per_group=pt)
+            assert np.array_equal(r.evaluate(x), want), (layout, pt)
+    mpair = synth.shell_pair(seed=3, side=40)
+    m = _reg(smc, mpair, config.default_params("dice", 21, 2, 15.0, 5.0))
+    xm = _random_states(21, 15, 5, 9)
+    wm = _oracle_sums(orc, orc.Volume(mpair["src"]), orc.Volume(mpair["tgt"]), xm, "mask")
+    for pt in (4, 8, 16):
+        m.tune(None, pt)
+        assert np.array_equal(m.evaluate(xm), wm), pt
+    with pytest.raises(smc.SmcError):
+        m.tune(None, 5)
+
+
+def test_batch_pairs_equal_single_runs_across_replays(smc, orc):
+    """Uneven pairs (mask and trilinear image, different sizes, particle and
+    iteration counts) in one graph launch: every pair equals its own
+    single-context run bit for bit, on several replays with new seeds and
+    eager work in between; one mask pair also against the oracle."""
+    specs = [("mask", 40, 96, 4), ("image", 33, 64, 3), ("mask", 28, 33, 5), ("image", 45, 130, 4),
+             ("mask", 52, 17, 2), ("image", 24, 40, 5)]
+    pairs, host = [], []
+    for i, (kind, side, n, K) in enumerate(specs):
+        if kind == "mask":
+            pr = synth.shell_pair(seed=30 + i, side=side)
+            prm = config.default_params("dice", n, K, 15.0, 4.0, seed=100 + i, pair_id=i)
+            pairs.append(dict(src=dev(pr["src"]), tgt=dev(pr["tgt"]), params=prm))
+        else:
+            pr = synth.speckle_pair(side=side, seed=30 + i, trans=3.0)
+            prm = config.default_params("ncc", n, K, 20.0, 3.0, seed=100 + i, pair_id=i)
+            pairs.append(dict(src=dev(pr["src"]), tgt=dev(pr["tgt"]), src_fov=dev(pr["src_fov"]), params=prm))
+        host.append((pr, prm))
+    b = smc.Batch(pairs)
+    for rep in range(3):
+        seeds = [1000 * rep + 7 * i for i in range(len(specs))]
+        b.set_seeds(seeds)
+        b.run()
+        for i, (pr, prm) in enumerate(host):
+            prm = dict(prm, seed=seeds[i])
+            r = _reg(smc, pr, prm, src_fov=pr.get("src_fov"))
+            r.run()
+            gb, gs = b.particles(i), r.particles()
+            assert np.array_equal(gb["states"], gs["states"]), (rep, i)
+            assert np.array_equal(gb["ancestors"], gs["ancestors"]), (rep, i)
+            assert np.array_equal(b.trace(i)["score"], r.trace()["score"]), (rep, i)
+            assert np.array_equal(b.estimate(i)["params"], r.estimate()["params"]), (rep, i)
+            r.close()
+        pr, prm = host[0]
+        o = orc.smc_run(pr["src"], pr["tgt"], dict(prm, seed=seeds[0]))
+        assert np.array_equal(b.particles(0)["ancestors"], o["ancestors"])
+        _assert_final_close(orc, b.estimate(0)["params"], o["est"])
+    b.close()
