@@ -121,6 +121,15 @@ smc_status smc_trace(smc_ctx *ctx, double *score_k1, double *ess_k, double *est_
  * but must not overlap smc_step on the same context.  Syncs. */
 smc_status smc_evaluate(smc_ctx *ctx, const double *states_n6, uint32_t n, int64_t *moments_n6);
 
+/* Exhaustive search (the EX baseline of Baseline and Evaluation Metrics):
+ * score every point of the regular grid x_d = lo[d] + step[d] c_d,
+ * c_d = 0 .. count[d] - 1 (axis 0 fastest), with the context's score, and
+ * return the best point (ties: lowest grid index) and its score.  scores
+ * (host, prod(count) doubles) may be NULL.  Uses the smc_evaluate workspace;
+ * must not overlap smc_step on the same context.  Syncs. */
+smc_status smc_exhaustive(smc_ctx *ctx, const double lo[6], const double step[6], const uint32_t count[6],
+                          double best_params[6], double *best_score, double *scores);
+
 /* Replace the particle set (host N x 6) as if k_done iterations had run;
  * for step-by-step replays and resumption.  Async. */
 smc_status smc_set_particles(smc_ctx *ctx, const double *states_n6, uint32_t k_done);
@@ -163,6 +172,46 @@ void smc_destroy(smc_ctx *ctx);
 smc_status warp_apply(const smc_volume *src, const double mat3x4[12], int32_t interp, uint8_t *dst,
                       int32_t nx, int32_t ny, int32_t nz, double sx, double sy, double sz, uint32_t n_frames,
                       int64_t src_frame_stride, int64_t dst_frame_stride, void *hip_stream);
+
+/* ---- Learned proposal (the machine-learning direction of the Conclusion).
+ * A 3D CNN reads the source / target pair downsampled to 64^3 (FP16, two
+ * channels) and predicts, in units of the limits, a Gaussian over the
+ * transform: 6 means and 6 log-variances.  Four 3x3x3 stride-2
+ * convolutions (2 -> 16 -> 32 -> 64 -> 64 channels, zero padding 1, bias,
+ * ReLU; bfloat16 weights and activations, FP32 accumulation on the matrix
+ * cores), flatten (channel-major) and a linear head 4096 -> 12 (FP32).
+ * Trained with the Gaussian negative log-likelihood of the filter's final
+ * weighted particle cloud, 0.5 sum_d [(var_d + (xbar_d - mu_d)^2) e^-l_d + l_d]
+ * averaged over the batch, and Adam (beta 0.9 / 0.999, eps 1e-8).
+ * Flat parameter layout (229,916 FP32): W1[16][2][27] b1[16] W2[32][16][27]
+ * b2[32] W3[64][32][27] b3[64] W4[64][64][27] b4[64] Wh[12][4096] bh[12], the
+ * 27 kernel taps ordered (kz, ky, kx). */
+typedef struct smc_cnn smc_cnn;
+
+/* Workspaces for batches of up to max_batch (1 .. 1024) pairs. */
+smc_status smc_cnn_create(smc_cnn **out, uint32_t max_batch, void *hip_stream);
+smc_status smc_cnn_set_params(smc_cnn *net, const float *host_params, size_t n);   /* syncs; resets Adam */
+smc_status smc_cnn_get_params(smc_cnn *net, float *host_params, size_t n);         /* syncs */
+/* Downsample a source / target pair into input slot `slot`: trilinear at
+ * half-pixel centres to 64^3, times `scale`, stored as FP16. */
+smc_status smc_cnn_input(smc_cnn *net, uint32_t slot, const smc_volume *src, const smc_volume *tgt, float scale);
+/* Copy input slot `slot` (2 x 64^3 FP16 bit patterns, source then target) to
+ * the host.  Syncs. */
+smc_status smc_cnn_read_input(smc_cnn *net, uint32_t slot, uint16_t *host);
+/* Outputs of slots 0 .. B-1: B x 12 (6 means, 6 log-variances), host.  Syncs. */
+smc_status smc_cnn_forward(smc_cnn *net, uint32_t B, float *out_host);
+/* Forward + backward of slots 0 .. B-1 against targets (B x 12 host: the
+ * cloud's means then variances, in units of the limits).  Returns the loss;
+ * grads_host (229,916 floats) may be NULL.  Syncs. */
+smc_status smc_cnn_backward(smc_cnn *net, uint32_t B, const float *target_host, float *loss, float *grads_host);
+/* One Adam step with the gradients of the last smc_cnn_backward. */
+smc_status smc_cnn_step(smc_cnn *net, float lr);
+void smc_cnn_destroy(smc_cnn *net);
+
+/* Draw the next prior (smc_reset) from the Gaussian N(mean, exp(logvar))
+ * truncated to x0 +- limit instead of the uniform box, and correct the first
+ * update by log p - log q.  mean == NULL returns to the uniform prior. */
+smc_status smc_set_proposal(smc_ctx *ctx, const double mean[6], const double logvar[6]);
 
 /* ---- Batches: many registration pairs of uneven size and particle count
  * run together.  Every pair behaves exactly as its own smc_init /

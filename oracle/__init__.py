@@ -46,7 +46,8 @@ class _Params(C.Structure):
                 ("pair_id", C.c_uint32), ("score", C.c_int32), ("trilinear", C.c_int32),
                 ("fp64_mode", C.c_int32), ("x0", C.c_double * 6), ("limit", C.c_double * 6),
                 ("sigma_score", C.c_double), ("sigma0", C.c_double * 6), ("anneal", C.c_double),
-                ("min_overlap_frac", C.c_double)]
+                ("min_overlap_frac", C.c_double), ("has_proposal", C.c_int32), ("prop_mu", C.c_double * 6),
+                ("prop_sigma", C.c_double * 6)]
 
 
 class _Problem(C.Structure):
@@ -89,7 +90,9 @@ def lib():
             "or_perturb": (None, [P(_Params), C.c_uint32, d, i32, d]),
             "or_init_particles": (None, [P(_Params), d]),
             "or_resample_word": (C.c_uint32, [P(_Params), C.c_uint32]),
-            "or_filter_update": (C.c_int, [P(_Params), C.c_uint32, d, d, d, d, d, P(C.c_double), i32, d]),
+            "or_filter_update": (C.c_int, [P(_Params), C.c_uint32, d, d, C.c_void_p, d, d, d, P(C.c_double), i32,
+                                           d]),
+            "or_init_proposal": (None, [P(_Params), d, d]),
             "or_smc_run": (C.c_int, [P(_Vol), P(_Vol), P(_Params), d, d, d, d, d, d, i32]),
             "or_warp_apply": (None, [P(_Vol), d, C.c_int, u8, C.c_int32, C.c_int32, C.c_int32,
                                      C.c_double, C.c_double, C.c_double]),
@@ -147,6 +150,13 @@ def make_params(p: dict, fp64_mode: bool = False) -> _Params:
     out.sigma0[:] = [float(v) for v in p["sigma0"]]
     out.anneal = float(p.get("anneal", 0.9))
     out.min_overlap_frac = float(p.get("min_overlap_frac", 0.05))
+    prop = p.get("proposal")
+    if prop is not None:
+        out.has_proposal = 1
+        out.prop_mu[:] = [float(v) for v in prop["mean"]]
+        # sigma = exp(logvar / 2), computed the same way on every side
+        import math
+        out.prop_sigma[:] = [math.exp(0.5 * float(v)) for v in prop["logvar"]]
     return out
 
 
@@ -274,6 +284,14 @@ def init_particles(params: dict) -> np.ndarray:
     return x
 
 
+def init_proposal(params: dict):
+    pr = make_params(params)
+    x = np.zeros((pr.n_particles, 6))
+    lq = np.zeros(pr.n_particles)
+    lib().or_init_proposal(C.byref(pr), x, lq)
+    return x, lq
+
+
 def resample_word(params: dict, k: int) -> int:
     return lib().or_resample_word(C.byref(make_params(params)), int(k))
 
@@ -317,7 +335,7 @@ def filter_update(params: dict, k: int, x, z) -> dict:
     anc = np.full(n, -1, np.int32)
     xn = np.zeros_like(x)
     ess = C.c_double()
-    deg = lib().or_filter_update(C.byref(pr), int(k), x, z, lw, w, est, C.byref(ess), anc, xn)
+    deg = lib().or_filter_update(C.byref(pr), int(k), x, z, None, lw, w, est, C.byref(ess), anc, xn)
     return dict(lw=lw, w=w, est=est, ess=ess.value, anc=anc, x_next=xn, degenerate=bool(deg))
 
 

@@ -480,6 +480,9 @@ typedef struct {
     double sigma0[6];
     double anneal;
     double min_overlap_frac;
+    /* learned proposal: prior from N(prop_mu, prop_sigma^2) truncated to the box */
+    int32_t has_proposal;
+    double prop_mu[6], prop_sigma[6];
 } or_params;
 
 typedef struct {
@@ -662,6 +665,49 @@ void or_perturb(const or_params *pr, uint32_t k, const double *x_old, const int3
     }
 }
 
+/* Proposal draw: per axis, the first of 16 tries mu + sigma g (g from
+ * Box-Muller on Philox tag 3, counter word 1 = try) that lands in the box, or
+ * mu clamped to the box; lq_i = sum_d ((x_d - mu_d) / sigma_d)^2 / 2, i.e.
+ * -log q(x_i) up to a constant (the truncated Gaussian's normaliser). */
+static void init_proposal(const or_params *pr, double *x, double *lq)
+{
+    for (uint32_t i = 0; i < pr->n_particles; ++i) {
+        double p[6];
+        int done[6] = {0, 0, 0, 0, 0, 0};
+        for (int d = 0; d < 6; ++d) {
+            double lo = pr->x0[d] - pr->limit[d], hi = pr->x0[d] + pr->limit[d];
+            p[d] = fmin(fmax(pr->prop_mu[d], lo), hi);
+        }
+        for (uint32_t t = 0; t < 16; ++t) {
+            double g[6];
+            for (uint32_t b = 0; b < 3; ++b) {
+                uint32_t r[4];
+                draw(pr->seed, i, t, pr->pair_id, OR_TAG_PROPOSAL, b, r);
+                double u1 = or_u53(r[0], r[1]), u2 = or_u53(r[2], r[3]);
+                double rad = sqrt(-2.0 * log(u1));
+                double th = 6.283185307179586 * u2;
+                g[2 * b] = rad * cos(th);
+                g[2 * b + 1] = rad * sin(th);
+            }
+            for (int d = 0; d < 6; ++d) {
+                double lo = pr->x0[d] - pr->limit[d], hi = pr->x0[d] + pr->limit[d];
+                double v = pr->prop_mu[d] + pr->prop_sigma[d] * g[d];
+                if (!done[d] && v >= lo && v <= hi) {
+                    p[d] = v;
+                    done[d] = 1;
+                }
+            }
+        }
+        double q = 0.0;
+        for (int d = 0; d < 6; ++d) {
+            double z = (p[d] - pr->prop_mu[d]) / pr->prop_sigma[d];
+            q += 0.5 * (z * z);
+        }
+        lq[i] = q;
+        memcpy(x + 6 * (size_t)i, p, sizeof p);
+    }
+}
+
 /* Prior draw: x_i = x0 + L (2u - 1), u from Philox tag 0. */
 void or_init_particles(const or_params *pr, double *x)
 {
@@ -675,6 +721,8 @@ void or_init_particles(const or_params *pr, double *x)
             x[6 * (size_t)i + d1] = pr->x0[d1] + pr->limit[d1] * (2.0 * ub - 1.0);
         }
 }
+
+void or_init_proposal(const or_params *pr, double *x, double *lq) { init_proposal(pr, x, lq); }
 
 uint32_t or_resample_word(const or_params *pr, uint32_t k)
 {
@@ -692,11 +740,15 @@ void or_score_particles(const or_problem *pb, const or_params *pr, uint32_t n, c
 
 /* One filter update after the scores of iteration k are known:
  * weights -> normalise / estimate -> (k < K) resample and predict. */
-int or_filter_update(const or_params *pr, uint32_t k, const double *x, const double *z, double *lw, double *w,
-                     double est[6], double *ess, int32_t *anc, double *x_next)
+int or_filter_update(const or_params *pr, uint32_t k, const double *x, const double *z, const double *lq,
+                     double *lw, double *w, double est[6], double *ess, int32_t *anc, double *x_next)
 {
     uint32_t n = pr->n_particles;
-    for (uint32_t i = 0; i < n; ++i) lw[i] = or_loglik(z[i], pr->score, pr->sigma_score);
+    for (uint32_t i = 0; i < n; ++i) {
+        lw[i] = or_loglik(z[i], pr->score, pr->sigma_score);
+        /* importance correction of the proposal draw: log p - log q, p uniform */
+        if (k == 1 && pr->has_proposal && lq) lw[i] = lw[i] + lq[i];
+    }
     int degen = or_normalise(n, lw, x, w, est, ess);
     if (k < pr->n_iters) {
         or_resample(n, w, or_resample_word(pr, k), anc);
@@ -722,16 +774,18 @@ int or_smc_run(const or_vol *src, const or_vol *tgt, const or_params *pr, double
     double *lw = (double *)malloc(sizeof(double) * n);
     double *w = (double *)malloc(sizeof(double) * n);
     int32_t *anc = (int32_t *)malloc(sizeof(int32_t) * n);
+    double *lq = (double *)calloc(n, sizeof(double));
     for (uint32_t i = 0; i < n; ++i) anc[i] = -1;
     double est[6];
     memcpy(est, pr->x0, sizeof est);
     int degen_any = 0;
-    or_init_particles(pr, x);
+    if (pr->has_proposal) init_proposal(pr, x, lq);
+    else or_init_particles(pr, x);
     for (uint32_t k = 1; k <= pr->n_iters; ++k) {
         or_score_particles(&pb, pr, n, x, z);
         if (trace_score) trace_score[k - 1] = or_score_particle(&pb, pr, est);
         double ess;
-        degen_any |= or_filter_update(pr, k, x, z, lw, w, est, &ess, anc, xn);
+        degen_any |= or_filter_update(pr, k, x, z, lq, lw, w, est, &ess, anc, xn);
         if (trace_ess) trace_ess[k - 1] = ess;
         if (trace_est) memcpy(trace_est + 6 * (k - 1), est, sizeof est);
         if (k < pr->n_iters) {
@@ -743,7 +797,7 @@ int or_smc_run(const or_vol *src, const or_vol *tgt, const or_params *pr, double
     if (x_out) memcpy(x_out, x, sizeof(double) * 6 * n);
     if (lw_out) memcpy(lw_out, lw, sizeof(double) * n);
     if (anc_out) memcpy(anc_out, anc, sizeof(int32_t) * n);
-    free(x); free(xn); free(z); free(lw); free(w); free(anc);
+    free(x); free(xn); free(z); free(lw); free(w); free(anc); free(lq);
     return degen_any;
 }
 

@@ -9,6 +9,7 @@ to the CPU: without the built library every call raises.
 from .binding import (  # noqa: F401
     EXPORTS,
     Batch,
+    Cnn,
     Registration,
     SmcError,
     lib,

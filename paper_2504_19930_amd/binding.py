@@ -27,7 +27,9 @@ EXPORTS = ("smc_init", "smc_reset", "smc_step", "smc_estimate", "smc_get_particl
            "smc_evaluate", "smc_set_particles", "smc_get_state", "smc_set_state", "smc_destroy",
            "warp_apply", "smc_last_error", "smc_version", "smc_profile", "smc_profile_read",
            "smc_set_tuning", "smc_get_tuning", "smc_batch_init", "smc_batch_set_seeds", "smc_batch_run",
-           "smc_batch_pair", "smc_batch_destroy")
+           "smc_batch_pair", "smc_batch_destroy", "smc_cnn_create", "smc_cnn_set_params", "smc_cnn_get_params",
+           "smc_cnn_input", "smc_cnn_read_input", "smc_cnn_forward", "smc_cnn_backward", "smc_cnn_step", "smc_cnn_destroy",
+           "smc_set_proposal", "smc_exhaustive")
 
 
 class SmcError(RuntimeError):
@@ -80,6 +82,16 @@ def lib():
             "smc_batch_init": [P(vp), u32, vp, vp, vp, vp],
             "smc_batch_set_seeds": [vp, vp],
             "smc_batch_run": [vp],
+            "smc_cnn_create": [P(vp), u32, vp],
+            "smc_cnn_set_params": [vp, vp, C.c_size_t],
+            "smc_cnn_get_params": [vp, vp, C.c_size_t],
+            "smc_cnn_input": [vp, u32, P(SmcVolume), P(SmcVolume), C.c_float],
+            "smc_cnn_forward": [vp, u32, vp],
+            "smc_cnn_read_input": [vp, u32, vp],
+            "smc_cnn_backward": [vp, u32, vp, vp, vp],
+            "smc_cnn_step": [vp, C.c_float],
+            "smc_set_proposal": [vp, vp, vp],
+            "smc_exhaustive": [vp, vp, vp, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -91,6 +103,8 @@ def lib():
         L.smc_batch_pair.restype = vp
         L.smc_batch_destroy.argtypes = [vp]
         L.smc_batch_destroy.restype = None
+        L.smc_cnn_destroy.argtypes = [vp]
+        L.smc_cnn_destroy.restype = None
         L.smc_last_error.restype = C.c_char_p
         L.smc_version.restype = C.c_char_p
         _lib = L
@@ -237,6 +251,26 @@ def smc_profile_read(ctx) -> dict:
 LAYOUTS = {"raw": 0, "pairx": 1, "quadxy": 2, "oct": 3}
 
 
+def smc_exhaustive(ctx, lo, step, count, want_scores=False) -> dict:
+    lo_ = np.ascontiguousarray(lo, dtype=np.float64)
+    st = np.ascontiguousarray(step, dtype=np.float64)
+    cn = np.ascontiguousarray(count, dtype=np.uint32)
+    best, score = np.zeros(6), C.c_double()
+    scores = np.zeros(int(np.prod(cn.astype(np.int64)))) if want_scores else None
+    _check(lib().smc_exhaustive(ctx, _ptr(lo_), _ptr(st), _ptr(cn), _ptr(best), C.cast(C.byref(score), C.c_void_p),
+                                None if scores is None else _ptr(scores)))
+    return dict(params=best, score=score.value, scores=scores)
+
+
+def smc_set_proposal(ctx, mean=None, logvar=None):
+    if mean is None:
+        _check(lib().smc_set_proposal(ctx, None, None))
+        return
+    m = np.ascontiguousarray(mean, dtype=np.float64)
+    lv = np.ascontiguousarray(logvar, dtype=np.float64)
+    _check(lib().smc_set_proposal(ctx, _ptr(m), _ptr(lv)))
+
+
 def smc_set_tuning(ctx, layout=None, particles_per_group=None):
     lay = -1 if layout is None else (LAYOUTS[layout] if isinstance(layout, str) else int(layout))
     pt = -1 if particles_per_group is None else int(particles_per_group)
@@ -296,6 +330,12 @@ class Registration:
 
     def set_state(self, blob):
         smc_set_state(self.ctx, blob)
+
+    def exhaustive(self, lo, step, count, want_scores=False):
+        return smc_exhaustive(self.ctx, lo, step, count, want_scores)
+
+    def set_proposal(self, mean=None, logvar=None):
+        smc_set_proposal(self.ctx, mean, logvar)
 
     def tune(self, layout=None, particles_per_group=None):
         smc_set_tuning(self.ctx, layout, particles_per_group)
@@ -367,6 +407,63 @@ class Batch:
         if self.b:
             lib().smc_batch_destroy(self.b)
             self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+CNN_PARAMS = 229916
+
+
+class Cnn:
+    """The learned-proposal network (smc_cnn_*): bfloat16 MFMA convolutions,
+    FP32 head, Gaussian-NLL backward and Adam, all on the GPU."""
+
+    def __init__(self, max_batch=32, stream=None):
+        self.net = C.c_void_p()
+        _check(lib().smc_cnn_create(C.byref(self.net), int(max_batch), _stream_handle(stream)))
+        self.max_batch = int(max_batch)
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        _check(lib().smc_cnn_set_params(self.net, _ptr(a), a.size))
+
+    def get_params(self):
+        a = np.zeros(CNN_PARAMS, np.float32)
+        _check(lib().smc_cnn_get_params(self.net, _ptr(a), a.size))
+        return a
+
+    def input(self, slot, src: SmcVolume, tgt: SmcVolume, scale=1.0):
+        _check(lib().smc_cnn_input(self.net, int(slot), C.byref(src), C.byref(tgt), float(scale)))
+
+    def read_input(self, slot):
+        a = np.zeros((2, 64, 64, 64), np.uint16)
+        _check(lib().smc_cnn_read_input(self.net, int(slot), _ptr(a)))
+        return a.view(np.float16)
+
+    def forward(self, B):
+        out = np.zeros((B, 12), np.float32)
+        _check(lib().smc_cnn_forward(self.net, int(B), _ptr(out)))
+        return out
+
+    def backward(self, target, grads=False):
+        t = np.ascontiguousarray(target, dtype=np.float32).reshape(-1, 12)
+        loss = C.c_float()
+        g = np.zeros(CNN_PARAMS, np.float32) if grads else None
+        _check(lib().smc_cnn_backward(self.net, len(t), _ptr(t), C.cast(C.byref(loss), C.c_void_p),
+                                      None if g is None else _ptr(g)))
+        return (loss.value, g) if grads else loss.value
+
+    def step(self, lr):
+        _check(lib().smc_cnn_step(self.net, float(lr)))
+
+    def close(self):
+        if self.net:
+            lib().smc_cnn_destroy(self.net)
+            self.net = None
 
     def __del__(self):
         try:

@@ -412,6 +412,69 @@ smc_status smc_evaluate(smc_ctx *c, const double *states, uint32_t n, int64_t *m
     return SMC_OK;
 }
 
+smc_status smc_exhaustive(smc_ctx *c, const double lo[6], const double step[6], const uint32_t count[6],
+                          double best_params[6], double *best_score, double *scores) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (!lo || !step || !count) return fail(SMC_EINVAL, "lo, step and count must not be NULL");
+    if (!finite6(lo) || !finite6(step)) return fail(SMC_EINVAL, "grid must be finite");
+    uint64_t total = 1;
+    for (int d = 0; d < 6; ++d) {
+        if (count[d] < 1) return fail(SMC_EINVAL, "count[%d] must be >= 1", d);
+        total *= count[d];
+        if (total > ((uint64_t)1 << 40)) return fail(SMC_EINVAL, "grid too large");
+    }
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    const uint32_t chunk = (uint32_t)std::min<uint64_t>(total, 8192);
+    if ((st = ensure_eval(c, chunk)) != SMC_OK) return c->mark(st);
+    const uint64_t n_chunks = (total + chunk - 1) / chunk;
+    double *dz = nullptr, *dscores = nullptr;
+    unsigned long long *di = nullptr;
+    if ((st = c->alloc(&dz, n_chunks)) != SMC_OK || (st = c->alloc(&di, n_chunks)) != SMC_OK) return c->mark(st);
+    if (scores && (st = c->alloc(&dscores, total)) != SMC_OK) return c->mark(st);
+    for (uint64_t q = 0; q < n_chunks; ++q) {
+        const uint64_t first = q * chunk;
+        const uint32_t n = (uint32_t)std::min<uint64_t>(chunk, total - first);
+        HIP_TRY(launch_grid_words(lo, step, count, first, n, c->f.geom, c->f.nearest, c->x_eval, c->w_eval,
+                                  c->stream));
+        HIP_TRY(launch_fill_u64(c->s_eval, 6ull * n, c->stream));
+        HIP_TRY(launch_score(c->score_launch(c->w_eval, c->s_eval, 0, n), c->stream));
+        HIP_TRY(launch_chunk_best(c->s_eval, n, first, c->f.sc, dscores ? dscores + first : nullptr, dz + q, di + q,
+                                  c->stream));
+    }
+    std::vector<double> hz(n_chunks);
+    std::vector<unsigned long long> hi(n_chunks);
+    HIP_TRY(hipMemcpyAsync(hz.data(), dz, 8 * n_chunks, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(hi.data(), di, 8 * n_chunks, hipMemcpyDeviceToHost, c->stream));
+    if (scores) HIP_TRY(hipMemcpyAsync(scores, dscores, 8 * total, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    // the temporaries are released with the context (allocs list); drop them now
+    for (void *ptr : {(void *)dz, (void *)di, (void *)dscores}) {
+        if (!ptr) continue;
+        c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), ptr), c->allocs.end());
+        (void)hipFree(ptr);
+    }
+    double bz = -INFINITY;
+    unsigned long long bi = ~0ull;
+    for (uint64_t q = 0; q < n_chunks; ++q)
+        if (hz[q] > bz || (hz[q] == bz && hi[q] < bi)) {
+            bz = hz[q];
+            bi = hi[q];
+        }
+    if (bi == ~0ull) bi = 0;
+    if (best_params) {
+        uint64_t g = bi;
+        for (int d = 0; d < 6; ++d) {
+            const uint64_t cd = g % count[d];
+            g /= count[d];
+            best_params[d] = lo[d] + step[d] * (double)cd;
+        }
+    }
+    if (best_score) *best_score = bz;
+    return SMC_OK;
+}
+
 smc_status smc_estimate(smc_ctx *c, double params[6], double mat3x4[12], double *score, double *ess) {
     if (!c) return fail(SMC_EINVAL, "ctx is NULL");
     smc_status st;
@@ -886,6 +949,186 @@ void smc_batch_destroy(smc_batch *b) {
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
+}
+
+}  // extern "C"
+
+// ===================================================================== learned proposal
+
+struct smc_cnn {
+    hipStream_t stream = nullptr;
+    uint32_t max_batch = 0;
+    CnnBuffers c{};
+    uint16_t *input = nullptr;  // max_batch x 2 x 64^3 FP16
+    float *out = nullptr, *target = nullptr, *loss = nullptr;
+    int adam_t = 0;
+    std::vector<void *> allocs;
+    template <typename T>
+    smc_status alloc(T **p, size_t count) {
+        void *ptr = nullptr;
+        if (hipMalloc(&ptr, count * sizeof(T) > 0 ? count * sizeof(T) : 1) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SMC_ENOMEM, "hipMalloc failed in smc_cnn_create");
+        }
+        allocs.push_back(ptr);
+        *p = static_cast<T *>(ptr);
+        return SMC_OK;
+    }
+};
+
+extern "C" {
+
+smc_status smc_cnn_create(smc_cnn **out, uint32_t max_batch, void *hip_stream) {
+    g_err.clear();
+    if (!out) return fail(SMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_batch < 1 || max_batch > 1024) return fail(SMC_EINVAL, "max_batch must be in 1..1024");
+    smc_cnn *n = new (std::nothrow) smc_cnn();
+    if (!n) return fail(SMC_ENOMEM, "host allocation failed");
+    n->stream = (hipStream_t)hip_stream;
+    n->max_batch = max_batch;
+    CnnBuffers &c = n->c;
+    c.n_params = cnn_param_offset(10);
+    const size_t side3 = (size_t)kCnnSide * kCnnSide * kCnnSide;
+    smc_status st;
+    auto bail = [&](smc_status e) {
+        smc_cnn_destroy(n);
+        return e;
+    };
+    if ((st = n->alloc(&c.params, c.n_params)) != SMC_OK || (st = n->alloc(&c.grads, c.n_params)) != SMC_OK ||
+        (st = n->alloc(&c.adam_m, c.n_params)) != SMC_OK || (st = n->alloc(&c.adam_v, c.n_params)) != SMC_OK ||
+        (st = n->alloc(&c.wbf16, cnn_param_offset(8))) != SMC_OK ||
+        (st = n->alloc(&n->input, 2 * side3 * max_batch)) != SMC_OK ||
+        (st = n->alloc(&n->out, 12ull * max_batch)) != SMC_OK ||
+        (st = n->alloc(&n->target, 12ull * max_batch)) != SMC_OK || (st = n->alloc(&n->loss, 4)) != SMC_OK ||
+        (st = n->alloc(&c.dout, 12ull * max_batch)) != SMC_OK)
+        return bail(st);
+    for (int L = 0; L < 4; ++L) {
+        const size_t d = (size_t)(kCnnSide >> (L + 1));
+        const size_t elems = (size_t)max_batch * kCnnChannels[L + 1] * d * d * d;
+        if ((st = n->alloc(&c.act[L], elems)) != SMC_OK || (st = n->alloc(&c.dact[L], elems)) != SMC_OK)
+            return bail(st);
+    }
+    std::vector<float> zeros((size_t)c.n_params, 0.0f);
+    if (hipMemcpy(c.params, zeros.data(), 4 * c.n_params, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.adam_m, zeros.data(), 4 * c.n_params, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.adam_v, zeros.data(), 4 * c.n_params, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.grads, zeros.data(), 4 * c.n_params, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(SMC_EDEVICE, "parameter initialisation failed"));
+    if (cnn_refresh_bf16(c, n->stream) != hipSuccess || hipStreamSynchronize(n->stream) != hipSuccess)
+        return bail(fail(SMC_EDEVICE, "parameter initialisation failed"));
+    *out = n;
+    return SMC_OK;
+}
+
+smc_status smc_cnn_set_params(smc_cnn *n, const float *host, size_t count) {
+    if (!n || !host) return fail(SMC_EINVAL, "net and params must not be NULL");
+    if (count != (size_t)n->c.n_params) return fail(SMC_EINVAL, "%zu parameters given, %lld expected", count,
+                                                    (long long)n->c.n_params);
+    for (size_t q = 0; q < count; ++q)
+        if (!isfinite(host[q])) return fail(SMC_EINVAL, "parameter %zu is not finite", q);
+    std::vector<float> zeros(count, 0.0f);
+    HIP_TRY(hipMemcpyAsync(n->c.params, host, 4 * count, hipMemcpyHostToDevice, n->stream));
+    HIP_TRY(hipMemcpyAsync(n->c.adam_m, zeros.data(), 4 * count, hipMemcpyHostToDevice, n->stream));
+    HIP_TRY(hipMemcpyAsync(n->c.adam_v, zeros.data(), 4 * count, hipMemcpyHostToDevice, n->stream));
+    HIP_TRY(cnn_refresh_bf16(n->c, n->stream));
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    n->adam_t = 0;
+    return SMC_OK;
+}
+
+smc_status smc_cnn_get_params(smc_cnn *n, float *host, size_t count) {
+    if (!n || !host) return fail(SMC_EINVAL, "net and params must not be NULL");
+    if (count != (size_t)n->c.n_params) return fail(SMC_EINVAL, "wrong parameter count");
+    HIP_TRY(hipMemcpyAsync(host, n->c.params, 4 * count, hipMemcpyDeviceToHost, n->stream));
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    return SMC_OK;
+}
+
+smc_status smc_cnn_input(smc_cnn *n, uint32_t slot, const smc_volume *src, const smc_volume *tgt, float scale) {
+    if (!n) return fail(SMC_EINVAL, "net is NULL");
+    if (slot >= n->max_batch) return fail(SMC_EINVAL, "slot %u beyond max_batch", slot);
+    if (!isfinite(scale)) return fail(SMC_EINVAL, "scale must be finite");
+    smc_status st;
+    if ((st = check_volume(src, "src")) != SMC_OK || (st = check_volume(tgt, "tgt")) != SMC_OK) return st;
+    const size_t side3 = (size_t)kCnnSide * kCnnSide * kCnnSide;
+    const int32_t sn[3] = {src->nx, src->ny, src->nz}, tn[3] = {tgt->nx, tgt->ny, tgt->nz};
+    HIP_TRY(cnn_downsample(src->data, sn, scale, n->input + 2 * side3 * slot, n->stream));
+    HIP_TRY(cnn_downsample(tgt->data, tn, scale, n->input + 2 * side3 * slot + side3, n->stream));
+    return SMC_OK;
+}
+
+smc_status smc_cnn_read_input(smc_cnn *n, uint32_t slot, uint16_t *host) {
+    if (!n || !host) return fail(SMC_EINVAL, "net and host must not be NULL");
+    if (slot >= n->max_batch) return fail(SMC_EINVAL, "slot %u beyond max_batch", slot);
+    const size_t side3 = (size_t)kCnnSide * kCnnSide * kCnnSide;
+    HIP_TRY(hipMemcpyAsync(host, n->input + 2 * side3 * slot, 4 * side3, hipMemcpyDeviceToHost, n->stream));
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    return SMC_OK;
+}
+
+smc_status smc_cnn_forward(smc_cnn *n, uint32_t B, float *out_host) {
+    if (!n || !out_host) return fail(SMC_EINVAL, "net and out must not be NULL");
+    if (B < 1 || B > n->max_batch) return fail(SMC_EINVAL, "batch %u outside 1..%u", B, n->max_batch);
+    HIP_TRY(cnn_forward(n->c, n->input, (int)B, n->out, n->stream));
+    HIP_TRY(hipMemcpyAsync(out_host, n->out, 48ull * B, hipMemcpyDeviceToHost, n->stream));
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    return SMC_OK;
+}
+
+smc_status smc_cnn_backward(smc_cnn *n, uint32_t B, const float *target_host, float *loss, float *grads_host) {
+    if (!n || !target_host) return fail(SMC_EINVAL, "net and target must not be NULL");
+    if (B < 1 || B > n->max_batch) return fail(SMC_EINVAL, "batch %u outside 1..%u", B, n->max_batch);
+    for (size_t q = 0; q < 12ull * B; ++q)
+        if (!isfinite(target_host[q]) || (q % 12 >= 6 && target_host[q] < 0.0f))
+            return fail(SMC_EINVAL, "target %zu must be finite (variances non-negative)", q);
+    HIP_TRY(hipMemcpyAsync(n->target, target_host, 48ull * B, hipMemcpyHostToDevice, n->stream));
+    HIP_TRY(cnn_forward(n->c, n->input, (int)B, n->out, n->stream));
+    HIP_TRY(cnn_backward(n->c, n->input, (int)B, n->out, n->target, n->loss, n->stream));
+    float l = 0.0f;
+    HIP_TRY(hipMemcpyAsync(&l, n->loss, 4, hipMemcpyDeviceToHost, n->stream));
+    if (grads_host)
+        HIP_TRY(hipMemcpyAsync(grads_host, n->c.grads, 4 * n->c.n_params, hipMemcpyDeviceToHost, n->stream));
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    if (loss) *loss = l;
+    return SMC_OK;
+}
+
+smc_status smc_cnn_step(smc_cnn *n, float lr) {
+    if (!n) return fail(SMC_EINVAL, "net is NULL");
+    if (!(lr > 0.0f) || !isfinite(lr)) return fail(SMC_EINVAL, "lr must be positive");
+    n->adam_t += 1;
+    HIP_TRY(cnn_adam(n->c, lr, n->adam_t, n->stream));
+    return SMC_OK;
+}
+
+void smc_cnn_destroy(smc_cnn *n) {
+    if (!n) return;
+    (void)hipStreamSynchronize(n->stream);
+    for (void *p : n->allocs) (void)hipFree(p);
+    delete n;
+}
+
+smc_status smc_set_proposal(smc_ctx *c, const double mean[6], const double logvar[6]) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (!mean) {
+        c->f.has_proposal = 0;
+        return SMC_OK;
+    }
+    if (!logvar) return fail(SMC_EINVAL, "logvar is NULL");
+    if (!finite6(mean) || !finite6(logvar)) return fail(SMC_EINVAL, "proposal must be finite");
+    for (int d = 0; d < 6; ++d)
+        if (logvar[d] < -60.0 || logvar[d] > 60.0) return fail(SMC_EINVAL, "logvar[%d] out of range", d);
+    if (!c->f.lq) {
+        smc_status st = c->alloc(&c->f.lq, c->f.n);
+        if (st != SMC_OK) return st;
+    }
+    c->f.has_proposal = 1;
+    for (int d = 0; d < 6; ++d) {
+        c->f.prop_mu[d] = mean[d];
+        c->f.prop_sigma[d] = exp(0.5 * logvar[d]);
+    }
+    return SMC_OK;
 }
 
 }  // extern "C"

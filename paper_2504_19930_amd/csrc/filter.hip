@@ -40,16 +40,54 @@ __global__ __launch_bounds__(256) void k_words(const double *x, uint32_t n, Geom
 }
 
 // Prior: x_i = x0 + L (2u - 1), u from Philox (tag 0, three blocks).
+constexpr uint32_t kProposalTries = 16;
+
+// Six standard normals of try t for particle i from the proposal stream.
+__device__ __forceinline__ void proposal_normals(const FilterState &f, uint32_t i, uint32_t t, double g[6]) {
+    for (uint32_t b = 0; b < 3; ++b) {
+        uint32_t r[4];
+        draw4(f.seed, i, t, f.pair, kTagProposal, b, r);
+        const double u1 = uniform53(r[0], r[1]), u2 = uniform53(r[2], r[3]);
+        const double rad = sqrt(-2.0 * log(u1));
+        const double th = 6.283185307179586 * u2;
+        g[2 * b] = rad * cos(th);
+        g[2 * b + 1] = rad * sin(th);
+    }
+}
+
 __device__ __forceinline__ void init_body(const FilterState &f, uint32_t i, uint32_t stride) {
     if (i < f.n) {
         double p[6];
-        for (uint32_t b = 0; b < 3; ++b) {
-            uint32_t r[4];
-            draw4(f.seed, i, 0u, f.pair, kTagInit, b, r);
-            const double ua = uniform53(r[0], r[1]), ub = uniform53(r[2], r[3]);
-            const int d0 = 2 * b, d1 = 2 * b + 1;
-            p[d0] = f.x0[d0] + f.limit[d0] * (2.0 * ua - 1.0);
-            p[d1] = f.x0[d1] + f.limit[d1] * (2.0 * ub - 1.0);
+        if (f.has_proposal) {
+            // per-axis rejection into the box (a product region), clamp after 16 tries
+            bool done[6] = {false, false, false, false, false, false};
+            for (int d = 0; d < 6; ++d) p[d] = fmin(fmax(f.prop_mu[d], f.lo[d]), f.hi[d]);
+            for (uint32_t t = 0; t < kProposalTries; ++t) {
+                double g[6];
+                proposal_normals(f, i, t, g);
+                for (int d = 0; d < 6; ++d) {
+                    const double v = f.prop_mu[d] + f.prop_sigma[d] * g[d];
+                    if (!done[d] && v >= f.lo[d] && v <= f.hi[d]) {
+                        p[d] = v;
+                        done[d] = true;
+                    }
+                }
+            }
+            double lq = 0.0;
+            for (int d = 0; d < 6; ++d) {
+                const double z = (p[d] - f.prop_mu[d]) / f.prop_sigma[d];
+                lq += 0.5 * (z * z);
+            }
+            f.lq[i] = lq;
+        } else {
+            for (uint32_t b = 0; b < 3; ++b) {
+                uint32_t r[4];
+                draw4(f.seed, i, 0u, f.pair, kTagInit, b, r);
+                const double ua = uniform53(r[0], r[1]), ub = uniform53(r[2], r[3]);
+                const int d0 = 2 * b, d1 = 2 * b + 1;
+                p[d0] = f.x0[d0] + f.limit[d0] * (2.0 * ua - 1.0);
+                p[d1] = f.x0[d1] + f.limit[d1] * (2.0 * ub - 1.0);
+            }
         }
         for (int d = 0; d < 6; ++d) f.x[6 * (size_t)i + d] = p[d];
         particle_words(p, f.geom, f.nearest, f.words + 12 * (size_t)i);
@@ -98,7 +136,8 @@ __device__ __forceinline__ void filter_body(const FilterState &f, const uint32_t
     for (uint32_t i = tid; i < n; i += kFT) {
         int64_t m[6];
         for (int q = 0; q < 6; ++q) m[q] = (int64_t)f.sums[6 * (size_t)i + q];
-        const double l = log_likelihood(score_from_sums(m, f.sc), f.sc);
+        double l = log_likelihood(score_from_sums(m, f.sc), f.sc);
+        if (k == 1 && f.has_proposal) l = l + f.lq[i];
         f.lw[i] = l;
         mx = fmax(mx, l);
     }

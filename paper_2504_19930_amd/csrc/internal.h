@@ -85,6 +85,11 @@ struct FilterState {
     double *trace_ess;        // K
     double *trace_est;        // 6 K
     int32_t *flags;           // [0] degenerate weights seen
+    // learned proposal: the prior draw comes from a Gaussian truncated to the
+    // limits box, and the first update adds log p - log q (p uniform)
+    int32_t has_proposal;
+    double prop_mu[6], prop_sigma[6];
+    double *lq;               // n: -log q(x_i) + const of the proposal draw
 };
 
 hipError_t launch_init_particles(const FilterState &f, hipStream_t s);
@@ -95,6 +100,33 @@ hipError_t launch_filter(const FilterState &f, uint32_t k, hipStream_t s);
 hipError_t launch_ghost_final(const FilterState &f, hipStream_t s);
 hipError_t launch_words(const double *x, uint32_t n, const Geom &g, bool nearest, float *words, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, hipStream_t s);
+
+// Learned proposal network (cnn.hip).
+extern const int kCnnChannels[5];
+extern const int kCnnSide;
+extern const int kCnnFlat;
+struct CnnBuffers {
+    float *params;       // FP32 master weights (flat; layout in smc.h)
+    uint16_t *wbf16;     // bfloat16 copy of the convolution part
+    float *grads, *adam_m, *adam_v;
+    int64_t n_params;
+    uint16_t *act[4];    // layer outputs after ReLU, bfloat16
+    float *dact[4];      // gradients w.r.t. layer pre-activations
+    float *dout;         // B x 12
+};
+int64_t cnn_param_offset(int part);
+hipError_t cnn_downsample(const uint8_t *vol, const int32_t n[3], float scale, uint16_t *out, hipStream_t s);
+hipError_t cnn_forward(const CnnBuffers &c, const uint16_t *input, int B, float *out, hipStream_t s);
+hipError_t cnn_backward(const CnnBuffers &c, const uint16_t *input, int B, const float *out, const float *target,
+                        float *loss_dev, hipStream_t s);
+hipError_t cnn_adam(const CnnBuffers &c, float lr, int t, hipStream_t s);
+hipError_t cnn_refresh_bf16(const CnnBuffers &c, hipStream_t s);
+
+// Exhaustive search (exhaustive.hip).
+hipError_t launch_grid_words(const double lo[6], const double step[6], const uint32_t count[6], uint64_t first,
+                             uint32_t n, const Geom &g, bool nearest, double *x, float *words, hipStream_t s);
+hipError_t launch_chunk_best(const unsigned long long *sums, uint32_t n, uint64_t first, const ScoreConst &sc,
+                             double *scores, double *best_z, unsigned long long *best_i, hipStream_t s);
 
 // warp_apply
 hipError_t launch_warp_apply(const uint8_t *src, const int32_t sn[3], const float w[12], bool trilinear,

@@ -22,4 +22,5 @@ from .volumes import (  # noqa: F401
     batch_pairs,
     make_batch_pair,
     proposal_pair,
+    lv_train_pair,
 )

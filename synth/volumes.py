@@ -279,3 +279,43 @@ def proposal_pair(seed, side=64, rot_deg=15.0, trans=8.0) -> dict:
     axes = np.array([22.0, 15.0, 11.0]) * f * (1.0 + rng.uniform(-0.1, 0.1, 3))
     gt = _sample_gt(rng, rot_deg, trans * f)
     return mask_pair((side, side, side), outer=tuple(axes), inner=None, gt=gt)
+
+
+# ----------------------------------------------------------------------------- proposal training
+
+LV_SHAPE = (224, 208, 176)
+
+
+def lv_train_pair(seed, shape_xyz=LV_SHAPE, side=64, rot_deg=15.0, trans=16.0, supersample=2) -> dict:
+    """A contracting-LV ED pair seen at the proposal network's sampling grid:
+    side^3 cells over the full shape_xyz volume (cell size s = n / side per
+    axis, centres at full-volume voxel coordinates (a + 0.5) s - 0.5), each
+    cell's value the fraction of supersample^3 sub-points inside the analytic
+    LV (as uint8 0..255), plus the binary masks (fraction >= 0.5) that the
+    filter registers with spacing s.  Same LV model and transform ranges as
+    lv_sequence at frame 0."""
+    rng = np.random.default_rng(seed)
+    gt = _sample_gt(rng, rot_deg, trans)
+    axes_ed = np.array([80.0, 45.0, 40.0]) * (1.0 + rng.uniform(-0.1, 0.1, 3))
+    n = np.asarray(shape_xyz, float)
+    c = 0.5 * (n - 1.0)
+    s = n / side
+    M = gt_matrix(gt, shape_xyz)
+    R, off = M[:3, :3], M[:3, 3]
+    sub = (np.arange(supersample) + 0.5) / supersample - 0.5
+    frac_t = np.zeros((side, side, side))
+    frac_s = np.zeros((side, side, side))
+    base = [(np.arange(side) + 0.5) * s[d] - 0.5 for d in range(3)]
+    for oz in sub:
+        for oy in sub:
+            for ox in sub:
+                z, y, x = np.meshgrid(base[2] + oz * s[2], base[1] + oy * s[1], base[0] + ox * s[0], indexing="ij")
+                frac_t += _ellipsoid_r2(x, y, z, c, axes_ed) <= 1.0
+                d = np.stack([x - off[0], y - off[1], z - off[2]], 0).reshape(3, -1)
+                p = (R.T @ d).reshape(3, *x.shape)
+                frac_s += _ellipsoid_r2(p[0], p[1], p[2], c, axes_ed) <= 1.0
+    k = float(supersample ** 3)
+    tgt = np.floor(frac_t / k * 255.0 + 0.5).astype(np.uint8)
+    src = np.floor(frac_s / k * 255.0 + 0.5).astype(np.uint8)
+    return dict(src=src, tgt=tgt, src_mask=(src >= 128).astype(np.uint8), tgt_mask=(tgt >= 128).astype(np.uint8),
+                gt=gt, spacing=tuple(float(v) for v in s))

@@ -1,0 +1,144 @@
+"""GPU parity of the learned proposal: the MFMA convolution network's
+forward and backward against the FP64 oracle (same bfloat16 precision
+decisions; relative L2 error <= 2e-2), the downsampler, Adam, and the
+proposal-seeded filter against the oracle's."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cnn as ocnn
+from paper_2504_19930_amd import config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_19930_amd import binding
+    binding.lib()
+    return binding
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a, float).ravel(), np.asarray(b, float).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _inputs(smc, net, B, seed=0):
+    """B pairs into the network's input slots; returns the oracle's view of
+    the same input (FP16 storage, bfloat16 on use)."""
+    rng = np.random.default_rng(seed)
+    xs = []
+    keep = []
+    for b in range(B):
+        if b % 2 == 0:
+            pr = synth.proposal_pair(seed=seed * 100 + b)
+            s, t, scale = pr["src"], pr["tgt"], 1.0
+        else:
+            s = rng.integers(0, 256, (40, 50, 60)).astype(np.uint8)
+            t = rng.integers(0, 256, (70, 66, 64)).astype(np.uint8)
+            scale = 1.0 / 255.0
+        ts, tt = dev(s), dev(t)
+        keep += [ts, tt]
+        net.input(b, smc.volume(ts), smc.volume(tt), scale)
+        x = np.stack([ocnn.downsample(s, scale=scale), ocnn.downsample(t, scale=scale)])
+        xs.append(x)
+    x = np.stack(xs).astype(np.float16).astype(np.float32)
+    return ocnn.bf16(x).astype(np.float64), keep
+
+
+def _oracle_params(p32):
+    """The device computes convolutions with bfloat16 weights, the head in FP32."""
+    p = p32.astype(np.float32).copy()
+    n_conv = sum(int(np.prod(s)) for s in ocnn.param_shapes()[:8])
+    p[:n_conv] = ocnn.bf16(p[:n_conv])
+    return p.astype(np.float64)
+
+
+def test_forward_and_backward_match_oracle(smc):
+    B = 4
+    net = smc.Cnn(max_batch=B)
+    p32 = ocnn.init_params(3)
+    p32[ocnn.n_params() - 12:] = np.linspace(-0.5, 0.5, 12)  # nonzero head bias
+    net.set_params(p32)
+    x, keep = _inputs(smc, net, B)
+    out = net.forward(B)
+    po = _oracle_params(p32)
+    ref, acts = ocnn.forward(po, x, bf16_acts=True)
+    assert rel_l2(out, ref) <= 2e-2, rel_l2(out, ref)
+    rng = np.random.default_rng(1)
+    target = np.concatenate([rng.normal(0, 0.5, (B, 6)), rng.uniform(0.01, 0.2, (B, 6))], 1)
+    loss, g = net.backward(target, grads=True)
+    ref_loss = ocnn.nll(ref, target[:, :6], target[:, 6:])
+    assert abs(loss - ref_loss) <= 2e-2 * abs(ref_loss)
+    ref_g = ocnn.backward(po, acts, ocnn.nll_grad(ref, target[:, :6], target[:, 6:]))
+    offs = np.cumsum([0] + [int(np.prod(s)) for s in ocnn.param_shapes()])
+    for q in range(len(offs) - 1):
+        e = rel_l2(g[offs[q]:offs[q + 1]], ref_g[offs[q]:offs[q + 1]])
+        assert e <= 2e-2, (q, e)
+    assert np.array_equal(net.get_params(), p32)
+    net.close()
+
+
+def test_downsample_matches_oracle(smc):
+    net = smc.Cnn(max_batch=2)
+    rng = np.random.default_rng(4)
+    s = rng.integers(0, 256, (37, 81, 50)).astype(np.uint8)
+    t = synth.lv_sequence(seed=2, frames=[0], speckle=False)["tgt"]
+    ts, tt = dev(s), dev(t)
+    net.input(1, smc.volume(ts), smc.volume(tt), 1.0 / 255.0)
+    got = net.read_input(1).astype(np.float64)
+    for c, v in enumerate((s, t)):
+        ref = ocnn.downsample(v, scale=1.0 / 255.0)
+        # FP32 arithmetic then one FP16 rounding on the device
+        assert np.all(np.abs(got[c] - ref) <= 2.0 ** -10 * np.abs(ref) + 1e-6), c
+    net.close()
+
+
+def test_adam_training_reduces_loss(smc):
+    B = 8
+    net = smc.Cnn(max_batch=B)
+    p32 = ocnn.init_params(7)
+    net.set_params(p32)
+    x, keep = _inputs(smc, net, B, seed=2)
+    rng = np.random.default_rng(2)
+    target = np.concatenate([rng.normal(0, 0.3, (B, 6)), rng.uniform(0.01, 0.1, (B, 6))], 1)
+    first = net.backward(target)
+    for _ in range(30):
+        net.backward(target)
+        net.step(1e-3)
+    last = net.backward(target)
+    assert last < 0.5 * first, (first, last)
+    net.close()
+
+
+def test_proposal_prior_and_filter_match_oracle(smc, orc):
+    pair = synth.shell_pair(seed=6, side=40)
+    prm = config.default_params("dice", 96, 4, 15.0, 5.0, seed=21)
+    mean = np.array([0.05, -0.02, 0.03, 1.0, -0.5, 0.25])
+    logvar = 2 * np.log(np.array([0.03, 0.03, 0.03, 0.8, 0.8, 0.8]))
+    r = smc.Registration(dev(pair["src"]), dev(pair["tgt"]), prm)
+    r.set_proposal(mean, logvar)
+    r.reset(21)
+    p = dict(prm, proposal=dict(mean=list(mean), logvar=list(logvar)))
+    x, lq = orc.init_proposal(p)
+    # Box-Muller transcendentals may differ in the last bit between the two libms
+    assert np.allclose(r.particles()["states"], x, rtol=0, atol=1e-14)
+    r.run()
+    o = orc.smc_run(pair["src"], pair["tgt"], p)
+    g = r.particles()
+    assert np.array_equal(g["ancestors"], o["ancestors"])
+    assert np.allclose(g["states"], o["states"], rtol=0, atol=1e-12)
+    assert np.allclose(r.estimate()["params"], o["est"], atol=1e-12)
+    r.set_proposal(None)
+    r.reset(21)
+    assert np.array_equal(r.particles()["states"], orc.init_particles(prm))

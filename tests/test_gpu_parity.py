@@ -335,3 +335,25 @@ def test_batch_pairs_equal_single_runs_across_replays(smc, orc):
         assert np.array_equal(b.particles(0)["ancestors"], o["ancestors"])
         _assert_final_close(orc, b.estimate(0)["params"], o["est"])
     b.close()
+
+
+def test_exhaustive_search_matches_oracle_grid(smc, orc):
+    """The EX baseline: every grid score equals the oracle's (bit-exact Dice)
+    and the argmax is the truth on the 5^6 grid of the brute-force pin."""
+    import itertools
+    ang = np.deg2rad([-10, -5, 0, 5, 10])
+    gt = np.array([np.deg2rad(5), np.deg2rad(-5), 0.0, 1.0, -1.0, 2.0])
+    pair = synth.mask_pair((24, 24, 24), outer=(10.0, 7.0, 4.5), inner=None, gt=gt)
+    prm = config.default_params("dice", 16, 2, 12.5, 2.5)
+    r = _reg(smc, pair, prm)
+    lo = np.array([ang[0]] * 3 + [-2.0] * 3)
+    step = np.array([np.deg2rad(5)] * 3 + [1.0] * 3)
+    got = r.exhaustive(lo, step, [5] * 6, want_scores=True)
+    assert np.allclose(got["params"], gt)
+    # grid order: axis 0 fastest
+    grid = np.array([[lo[d] + step[d] * c[d] for d in range(6)]
+                     for c in (tuple(reversed(t)) for t in itertools.product(range(5), repeat=6))])
+    pb = orc.Problem(pair["src"], pair["tgt"])
+    ref = pb.score(prm, grid)
+    assert np.array_equal(got["scores"], ref)
+    assert got["score"] == ref.max()

@@ -201,3 +201,27 @@ def test_smc_recovers_image_transform_ncc(orc):
         errs.append((geodesic_deg(r["est"], pair["gt"], orc), np.linalg.norm(r["est"][3:] - pair["gt"][3:])))
     errs = np.array(errs)
     assert np.max(errs[:, 0]) <= 1.0 and np.max(errs[:, 1]) <= 1.0, errs
+
+
+def test_proposal_draw_and_importance_correction(orc):
+    """Truncated-Gaussian prior draw: inside the box, Gaussian away from the
+    walls; and exp(lq) are importance weights from q to the uniform prior
+    (self-normalised IS mean of x equals the box centre)."""
+    lim = np.array([0.3, 0.3, 0.3, 8.0, 8.0, 8.0])
+    x0 = np.array([0.05, -0.02, 0.0, 1.0, -2.0, 0.5])
+    mu = x0 + np.array([0.1, -0.05, 0.0, 2.0, 1.0, -1.5])
+    sd = np.array([0.02, 0.02, 0.02, 0.5, 0.5, 0.5])
+    p = _params(n_particles=20000, x0=list(x0), limit=list(lim),
+                proposal=dict(mean=list(mu), logvar=list(2 * np.log(sd))))
+    x, lq = orc.init_proposal(p)
+    assert np.all(np.abs(x - x0) <= lim + 1e-12)
+    for d in range(6):
+        assert stats.kstest((x[:, d] - mu[d]) / sd[d], "norm").pvalue > 0.01
+    assert np.allclose(lq, 0.5 * np.sum(((x - mu) / sd) ** 2, axis=1), rtol=1e-12)
+    wide = _params(n_particles=40000, x0=list(x0), limit=list(lim),
+                   proposal=dict(mean=list(mu), logvar=list(2 * np.log(lim * 0.8))))
+    xw, lqw = orc.init_proposal(wide)
+    w = np.exp(lqw - lqw.max())
+    est = (w[:, None] * xw).sum(0) / w.sum()
+    ess = w.sum() ** 2 / (w * w).sum()
+    assert np.all(np.abs(est - x0) < 4 * lim / np.sqrt(3 * ess)), (est, x0)
