@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--score", default="ncc", choices=["ncc", "ssd"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-time-to-dice", action="store_true")
+    ap.add_argument("--ttd-pairs", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the registration path "
@@ -162,6 +164,22 @@ def main():
                      "filter_ms_per_launch": prof["filter_ms"] / max(1, prof["filter_launches"])},
         "final_score": est["score"],
     }
+    if not args.no_time_to_dice:
+        from paper_2504_19930_amd import learned
+        if os.path.exists(learned.WEIGHTS):
+            log("time-to-Dice: learned proposal (N=512) vs plain filter (N=4096) ...")
+            params = learned.load_weights()
+            rows = []
+            for i in range(args.ttd_pairs):
+                lvp = synth.lv_sequence(seed=900000 + i, frames=[0], speckle=False)
+                rows.append(learned.time_to_dice(lvp, params, seed=i))
+            ratios = [r["ratio"] for r in rows if r["ratio"]]
+            line["time_to_dice"] = {
+                "metric": "time to Dice >= plain final Dice - 0.005, plain (N=4096) / learned (N=512)",
+                "median_ratio": float(np.median(ratios)) if ratios else None,
+                "reached": len(ratios), "pairs": len(rows),
+                "t_plain_ms": [r["t_plain_ms"] for r in rows], "t_learned_ms": [r["t_learned_ms"] for r in rows],
+                "workload": "224x208x176 ED LV masks, +-15 deg, +-16 voxels, K <= 40"}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         cb = cpu_baseline(pair, prm, args.cpu_seconds)

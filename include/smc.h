@@ -146,10 +146,14 @@ smc_status smc_set_state(smc_ctx *ctx, const void *buf, size_t len);
  * 1 x-pairs (uint16, four), 2 2x2 quads (uint32, two), 3 2x2x2 octets
  * (uint64, one); packed layouts cost 2, 4 or 8 bytes per source voxel of
  * device memory, prepared on the stream.  particles_per_group: particles
- * sharing one pass over a target column, 4, 8 or 16.  A negative value
- * keeps the current setting.  Defaults come from measurements on MI355X. */
-smc_status smc_set_tuning(smc_ctx *ctx, int32_t layout, int32_t particles_per_group);
-smc_status smc_get_tuning(smc_ctx *ctx, int32_t *layout, int32_t *particles_per_group);
+ * sharing one pass over a target column, 4, 8 or 16.  tile_depth: target
+ * slices per tile, 1 .. 256 (a tile is 32 x 8 x tile_depth voxels; shallower
+ * tiles cull more exactly -- a tile whose image cannot reach the source, or
+ * in the filter the source mask's bounding box, is skipped -- at the cost of
+ * more partial sums).  A negative value keeps the current setting.  Defaults
+ * come from measurements on MI355X. */
+smc_status smc_set_tuning(smc_ctx *ctx, int32_t layout, int32_t particles_per_group, int32_t tile_depth);
+smc_status smc_get_tuning(smc_ctx *ctx, int32_t *layout, int32_t *particles_per_group, int32_t *tile_depth);
 
 /* Kernel timing.  With enable != 0 every warp-and-score launch and every
  * filter launch of this context is bracketed by HIP events recorded on the

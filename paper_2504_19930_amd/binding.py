@@ -77,8 +77,8 @@ def lib():
             "warp_apply": [P(SmcVolume), vp, i32, vp, i32, i32, i32, dp, dp, dp, u32, i64, i64, vp],
             "smc_profile": [vp, i32],
             "smc_profile_read": [vp, vp, vp, vp, vp],
-            "smc_set_tuning": [vp, i32, i32],
-            "smc_get_tuning": [vp, vp, vp],
+            "smc_set_tuning": [vp, i32, i32, i32],
+            "smc_get_tuning": [vp, vp, vp, vp],
             "smc_batch_init": [P(vp), u32, vp, vp, vp, vp],
             "smc_batch_set_seeds": [vp, vp],
             "smc_batch_run": [vp],
@@ -271,16 +271,18 @@ def smc_set_proposal(ctx, mean=None, logvar=None):
     _check(lib().smc_set_proposal(ctx, _ptr(m), _ptr(lv)))
 
 
-def smc_set_tuning(ctx, layout=None, particles_per_group=None):
+def smc_set_tuning(ctx, layout=None, particles_per_group=None, tile_depth=None):
     lay = -1 if layout is None else (LAYOUTS[layout] if isinstance(layout, str) else int(layout))
     pt = -1 if particles_per_group is None else int(particles_per_group)
-    _check(lib().smc_set_tuning(ctx, lay, pt))
+    td = -1 if tile_depth is None else int(tile_depth)
+    _check(lib().smc_set_tuning(ctx, lay, pt, td))
 
 
 def smc_get_tuning(ctx) -> dict:
-    lay, pt = C.c_int32(), C.c_int32()
-    _check(lib().smc_get_tuning(ctx, C.cast(C.byref(lay), C.c_void_p), C.cast(C.byref(pt), C.c_void_p)))
-    return dict(layout=lay.value, particles_per_group=pt.value)
+    lay, pt, td = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().smc_get_tuning(ctx, C.cast(C.byref(lay), C.c_void_p), C.cast(C.byref(pt), C.c_void_p),
+                                C.cast(C.byref(td), C.c_void_p)))
+    return dict(layout=lay.value, particles_per_group=pt.value, tile_depth=td.value)
 
 
 def version() -> str:
@@ -337,8 +339,8 @@ class Registration:
     def set_proposal(self, mean=None, logvar=None):
         smc_set_proposal(self.ctx, mean, logvar)
 
-    def tune(self, layout=None, particles_per_group=None):
-        smc_set_tuning(self.ctx, layout, particles_per_group)
+    def tune(self, layout=None, particles_per_group=None, tile_depth=None):
+        smc_set_tuning(self.ctx, layout, particles_per_group, tile_depth)
 
     def tuning(self):
         return smc_get_tuning(self.ctx)

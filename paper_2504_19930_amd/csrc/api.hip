@@ -6,6 +6,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <limits.h>
+
 #include <algorithm>
 #include <new>
 #include <string>
@@ -23,6 +25,7 @@ thread_local std::string g_err;
 // Launch defaults (see smc_set_tuning).
 constexpr int kDefaultLayout = kLayoutRaw;
 constexpr int kDefaultPT = 8;
+constexpr int kDefaultZChunk = 32;
 
 smc_status fail(smc_status st, const char *fmt, ...) {
     char buf[512];
@@ -109,7 +112,8 @@ struct smc_ctx {
     int32_t sn[3] = {0, 0, 0}, tn[3] = {0, 0, 0};
     const uint8_t *src = nullptr, *src_fov = nullptr, *tgt = nullptr, *tgt_fov = nullptr;
     uint8_t *src_prep = nullptr, *tgt_prep = nullptr, *src_ok = nullptr;
-    int layout = kDefaultLayout, pt = kDefaultPT;
+    int layout = kDefaultLayout, pt = kDefaultPT, zchunk = kDefaultZChunk;
+    int32_t box_lo[3] = {1, 1, 1}, box_hi[3] = {-1, -1, -1};  // source mask bounding box (empty)
     void *packed[4] = {nullptr, nullptr, nullptr, nullptr};
     FilterState f{};
     uint32_t k_done = 0;
@@ -139,9 +143,17 @@ struct smc_ctx {
         return SMC_OK;
     }
 
-    ScoreLaunch score_launch(const float *words, unsigned long long *sums, uint32_t p0, uint32_t np) const {
+    // filter == true: only the sums the filter uses must be exact (masks: a, c)
+    ScoreLaunch score_launch(const float *words, unsigned long long *sums, uint32_t p0, uint32_t np,
+                             bool filter = false) const {
         ScoreLaunch L;
         L.mode = mode;
+        L.zchunk = zchunk;
+        L.cull_box = filter && mode == kModeMask;
+        for (int d = 0; d < 3; ++d) {
+            L.box_lo[d] = box_lo[d];
+            L.box_hi[d] = box_hi[d];
+        }
         if (mode == kModeMask) {
             L.src = src_prep;
             L.src_ok = nullptr;
@@ -306,6 +318,23 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
             return bail(fail(SMC_EDEVICE, "source packing launch failed"));
     }
 
+    if (c->mode == kModeMask) {
+        int32_t *dbox = nullptr;
+        const int32_t init[6] = {INT32_MAX, INT32_MAX, INT32_MAX, -1, -1, -1};
+        int32_t hb[6];
+        if ((st = c->alloc(&dbox, 6)) != SMC_OK) return bail(st);
+        if (hipMemcpyAsync(dbox, init, sizeof init, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            launch_mask_bbox(c->src_prep, c->sn, dbox, c->stream) != hipSuccess ||
+            hipMemcpyAsync(hb, dbox, sizeof hb, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return bail(fail(SMC_EDEVICE, "source mask bounding box failed"));
+        if (hb[3] >= 0)
+            for (int d = 0; d < 3; ++d) {
+                c->box_lo[d] = hb[d];
+                c->box_hi[d] = hb[3 + d];
+            }
+    }
+
     // exact per-volume sums -> statistics
     unsigned long long *vsum = nullptr;
     if ((st = c->alloc(&vsum, 8)) != SMC_OK) return bail(st);
@@ -377,8 +406,8 @@ smc_status smc_step(smc_ctx *c, uint32_t n_iters) {
     if ((uint64_t)c->k_done + n_iters > c->f.n_iters)
         return fail(SMC_ESTATE, "%u iterations requested, %u of %u already run", n_iters, c->k_done, c->f.n_iters);
     if ((st = set_device(c)) != SMC_OK) return c->mark(st);
-    const ScoreLaunch all = c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1);
-    const ScoreLaunch ghost = c->score_launch(c->f.words, c->f.sums, c->f.n, 1);
+    const ScoreLaunch all = c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true);
+    const ScoreLaunch ghost = c->score_launch(c->f.words, c->f.sums, c->f.n, 1, true);
     for (uint32_t it = 0; it < n_iters; ++it) {
         const uint32_t k = c->k_done + 1;
         hipError_t e = timed(c, c->ev_score, [&] { return launch_score(all, c->stream); });
@@ -439,7 +468,7 @@ smc_status smc_exhaustive(smc_ctx *c, const double lo[6], const double step[6], 
         HIP_TRY(launch_grid_words(lo, step, count, first, n, c->f.geom, c->f.nearest, c->x_eval, c->w_eval,
                                   c->stream));
         HIP_TRY(launch_fill_u64(c->s_eval, 6ull * n, c->stream));
-        HIP_TRY(launch_score(c->score_launch(c->w_eval, c->s_eval, 0, n), c->stream));
+        HIP_TRY(launch_score(c->score_launch(c->w_eval, c->s_eval, 0, n, true), c->stream));
         HIP_TRY(launch_chunk_best(c->s_eval, n, first, c->f.sc, dscores ? dscores + first : nullptr, dz + q, di + q,
                                   c->stream));
     }
@@ -606,8 +635,9 @@ smc_status smc_set_state(smc_ctx *c, const void *buf, size_t len) {
     return SMC_OK;
 }
 
-smc_status smc_set_tuning(smc_ctx *c, int32_t layout, int32_t pt) {
+smc_status smc_set_tuning(smc_ctx *c, int32_t layout, int32_t pt, int32_t tile_depth) {
     if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (tile_depth == 0 || tile_depth > 256) return fail(SMC_EINVAL, "tile_depth must be in 1..256");
     if (layout > kLayoutOct) return fail(SMC_EINVAL, "unknown layout %d", layout);
     if (pt >= 0 && !score_pt_supported(pt)) return fail(SMC_EINVAL, "particles_per_group must be 4, 8 or 16");
     smc_status st;
@@ -623,13 +653,15 @@ smc_status smc_set_tuning(smc_ctx *c, int32_t layout, int32_t pt) {
         c->layout = layout;
     }
     if (pt >= 0) c->pt = pt;
+    if (tile_depth > 0) c->zchunk = tile_depth;
     return SMC_OK;
 }
 
-smc_status smc_get_tuning(smc_ctx *c, int32_t *layout, int32_t *pt) {
+smc_status smc_get_tuning(smc_ctx *c, int32_t *layout, int32_t *pt, int32_t *tile_depth) {
     if (!c) return fail(SMC_EINVAL, "ctx is NULL");
     if (layout) *layout = c->layout;
     if (pt) *pt = c->pt;
+    if (tile_depth) *tile_depth = c->zchunk;
     return SMC_OK;
 }
 
@@ -766,7 +798,7 @@ smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode) {
     int pt = 8, layout = kLayoutRaw;
     for (uint32_t q = 0; q < n; ++q) {
         smc_ctx *c = b->pairs[C.members[q]];
-        const ScoreLaunch L = c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1);
+        const ScoreLaunch L = c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true);
         pt = L.pt;
         layout = L.layout;
         score_args(L, args.data() + ab * q);
@@ -824,12 +856,12 @@ smc_status record_run(smc_batch *b) {
         for (uint32_t i : b->singles) {
             smc_ctx *c = b->pairs[i];
             if (k <= c->f.n_iters)
-                HIP_TRY(launch_score(c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1), b->stream));
+                HIP_TRY(launch_score(c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true), b->stream));
         }
         HIP_TRY(launch_filter_batch(b->states_dev, (uint32_t)b->pairs.size(), k, b->stream));
         for (smc_ctx *c : b->pairs)
             if (c->f.n_iters == k) {
-                HIP_TRY(launch_score(c->score_launch(c->f.words, c->f.sums, c->f.n, 1), b->stream));
+                HIP_TRY(launch_score(c->score_launch(c->f.words, c->f.sums, c->f.n, 1, true), b->stream));
                 HIP_TRY(launch_ghost_final(c->f, b->stream));
             }
     }
@@ -878,7 +910,7 @@ smc_status smc_batch_init(smc_batch **out, uint32_t n_pairs, const smc_volume *s
     // one layout / particles-per-group for all trilinear pairs: the first pair's
     for (uint32_t q = 1; q < b->cls[1].members.size(); ++q) {
         smc_ctx *c0 = b->pairs[b->cls[1].members[0]], *c = b->pairs[b->cls[1].members[q]];
-        if ((st = smc_set_tuning(c, c0->layout, c0->pt)) != SMC_OK) return bail(st);
+        if ((st = smc_set_tuning(c, c0->layout, c0->pt, c0->zchunk)) != SMC_OK) return bail(st);
     }
     if ((st = b->alloc(&b->states_dev, n_pairs)) != SMC_OK) return bail(st);
     if (hipMemcpy(b->states_dev, b->states.data(), sizeof(FilterState) * n_pairs, hipMemcpyHostToDevice) != hipSuccess)

@@ -22,6 +22,11 @@ struct ScoreLaunch {
     const void *src_packed;   // trilinear: source in `layout` (nullptr = raw bytes)
     int layout;               // SourceLayout
     int pt;                   // particles per workgroup: 4, 8 or 16
+    int zchunk;               // target z-extent of a tile (0 = up to 256)
+    // masks: cull to the source mask's bounding box (exact for a and c only;
+    // n and b_ov then count only the tiles that reach it)
+    bool cull_box;
+    int32_t box_lo[3], box_hi[3];
     const uint8_t *src_ok;    // image: corner-valid bytes (source FOV) or nullptr
     const uint8_t *tgt;       // mask: prepared bits; image: intensities
     const uint8_t *tgt_fov;   // image: target FOV or nullptr
@@ -57,6 +62,9 @@ hipError_t launch_batch_score(const BatchPlan &P, uint32_t k, hipStream_t s);
 
 // Preparation of inputs.
 hipError_t launch_prep_mask(const uint8_t *vol, const uint8_t *fov, uint8_t *out, int64_t n, hipStream_t s);
+// Bounding box of the voxels with bit 1 set (mask on): out = {min x, y, z, max x, y, z};
+// initialise out to {INT_MAX x3, -1 x3}.
+hipError_t launch_mask_bbox(const uint8_t *prep, const int32_t n[3], int32_t *out, hipStream_t s);
 hipError_t launch_corner_valid(const uint8_t *fov, uint8_t *out, const int32_t n[3], hipStream_t s);
 // out[0..3] += (fov count, nonzero count, sum v, sum v^2) over the FOV
 hipError_t launch_volume_sums(const uint8_t *vol, const uint8_t *fov, int64_t n, unsigned long long *out,

@@ -3,6 +3,8 @@
 // (FOV voxel count, nonzero count, sum and sum of squares) from which the
 // host derives |T| for Dice, the minimum overlap and the mean-0 / std-1
 // normalisation statistics of Implementation Details.
+#include <stdint.h>
+
 #include "internal.h"
 
 namespace smc {
@@ -92,6 +94,24 @@ __global__ void k_pack_source(const uint8_t *vol, int32_t nx, int32_t ny, int32_
     }
 }
 
+__global__ void k_mask_bbox(const uint8_t *prep, int32_t nx, int32_t ny, int32_t nz, int32_t *out) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {-1, -1, -1};
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        if (!(prep[q] & 2u)) continue;
+        const int32_t c[3] = {(int32_t)(q % nx), (int32_t)((q / nx) % ny), (int32_t)(q / ((int64_t)nx * ny))};
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = min(lo[d], c[d]);
+            hi[d] = max(hi[d], c[d]);
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        if (hi[d] < 0) continue;
+        atomicMin(out + d, lo[d]);
+        atomicMax(out + 3 + d, hi[d]);
+    }
+}
+
 unsigned blocks_for(int64_t n) {
     int64_t b = (n + 255) / 256;
     return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
@@ -101,6 +121,12 @@ unsigned blocks_for(int64_t n) {
 
 hipError_t launch_prep_mask(const uint8_t *vol, const uint8_t *fov, uint8_t *out, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_prep_mask, dim3(blocks_for(n)), dim3(256), 0, s, vol, fov, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_bbox(const uint8_t *prep, const int32_t n[3], int32_t *out, hipStream_t s) {
+    const int64_t tot = (int64_t)n[0] * n[1] * n[2];
+    hipLaunchKernelGGL(k_mask_bbox, dim3(blocks_for(tot)), dim3(256), 0, s, prep, n[0], n[1], n[2], out);
     return hipGetLastError();
 }
 

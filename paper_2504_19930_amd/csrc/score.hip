@@ -16,6 +16,8 @@
 // addition is associative, so the result does not depend on scheduling.
 #include <string.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace smc {
@@ -35,7 +37,14 @@ struct KArgs {
     int32_t sn0, sn1, sn2, tn0, tn1, tn2;
     uint32_t p0, np;
     int32_t tiles_x, tiles_y, zchunk;
+    // exact culling: a particle can add to the sums of a tile only if the
+    // tile's image reaches the source-coordinate box [cull_lo, cull_hi]
+    float cull_lo[3], cull_hi[3];
 };
+
+// Culling margin (voxels): far above the FP32 rounding of the coordinate
+// recipe for any coordinate below 2^16.
+constexpr float kCullMargin = 0.0625f;
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
@@ -95,6 +104,40 @@ __device__ __forceinline__ void column_terms(const KArgs &a, const Tile &t, floa
     }
 }
 
+// Bit p set iff particle p's image of this tile (the box of target voxels
+// [i0, i1] x [j0, j1] x [k0, k1 - 1], mapped by the affine recipe, whose
+// extremes sit at the box corners) meets the cull box.  Uniform across the
+// workgroup.
+template <int PT>
+__device__ __forceinline__ uint32_t live_mask(const KArgs &a, const Tile &t, uint32_t bx) {
+    const int tiles = a.tiles_x * a.tiles_y;
+    const int b = (int)bx % tiles;
+    const int ty = b / a.tiles_x, tx = b - ty * a.tiles_x;
+    const float lo[3] = {(float)(tx * kTX), (float)(ty * kTY), (float)t.k0};
+    const float hi[3] = {(float)min(tx * kTX + kTX - 1, a.tn0 - 1), (float)min(ty * kTY + kTY - 1, a.tn1 - 1),
+                         (float)(t.k1 - 1)};
+    const uint32_t last = a.p0 + a.np - 1;
+    uint32_t live = 0;
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+        const float *w = a.words + 12 * (size_t)min(t.pbase + (uint32_t)p, last);
+        bool ok = p < t.npg;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            float umin = w[4 * d + 3], umax = w[4 * d + 3];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const float c0 = w[4 * d + e] * lo[e], c1 = w[4 * d + e] * hi[e];
+                umin += fminf(c0, c1);
+                umax += fmaxf(c0, c1);
+            }
+            ok = ok && umax + kCullMargin >= a.cull_lo[d] && umin - kCullMargin <= a.cull_hi[d];
+        }
+        live |= ok ? (1u << p) : 0u;
+    }
+    return live;
+}
+
 // ---------------------------------------------------------------- masks
 
 // Source byte: bit 0 = inside the source FOV, bit 1 = mask on (and in FOV).
@@ -104,6 +147,8 @@ __device__ __forceinline__ void column_terms(const KArgs &a, const Tile &t, floa
 template <int PT>
 __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t by) {
     const Tile t = tile_of<PT>(a, bx, by);
+    const uint32_t live = live_mask<PT>(a, t, bx);
+    if (live == 0u) return;  // nothing of this tile can reach the source region
     float mx[PT], my[PT], mz[PT], ax[PT], ay[PT], az[PT];
     column_terms<PT>(a, t, mx, my, mz, ax, ay, az);
     uint32_t acc1[PT], acc2[PT];
@@ -118,17 +163,26 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
             const uint32_t keep = (tb & 1u) ? 3u : 0u;
             const bool ton = (tb & 2u) != 0u;
             const float fk = (float)k;
+            // addresses of all PT samples first (outside: a safe address, result
+            // masked), then every load, then the sums: the loads overlap
+            uint32_t addr[PT];
+            bool in[PT];
 #pragma unroll
             for (int p = 0; p < PT; ++p) {
-                if (p < t.npg) {
-                    const int ix = (int)floorf(fmaf(ax[p], fk, mx[p]));
-                    const int iy = (int)floorf(fmaf(ay[p], fk, my[p]));
-                    const int iz = (int)floorf(fmaf(az[p], fk, mz[p]));
-                    uint32_t v = 0u;
-                    if ((uint32_t)ix < (uint32_t)a.sn0 && (uint32_t)iy < (uint32_t)a.sn1 &&
-                        (uint32_t)iz < (uint32_t)a.sn2)
-                        v = a.src[(uint32_t)ix + (uint32_t)a.sn0 * (uint32_t)iy + sn01 * (uint32_t)iz];
-                    v &= keep;
+                const int ix = (int)floorf(fmaf(ax[p], fk, mx[p]));
+                const int iy = (int)floorf(fmaf(ay[p], fk, my[p]));
+                const int iz = (int)floorf(fmaf(az[p], fk, mz[p]));
+                in[p] = (uint32_t)ix < (uint32_t)a.sn0 && (uint32_t)iy < (uint32_t)a.sn1 &&
+                        (uint32_t)iz < (uint32_t)a.sn2;
+                addr[p] = in[p] ? (uint32_t)ix + (uint32_t)a.sn0 * (uint32_t)iy + sn01 * (uint32_t)iz : 0u;
+            }
+            uint32_t val[PT];
+#pragma unroll
+            for (int p = 0; p < PT; ++p) val[p] = (live >> p) & 1u ? a.src[addr[p]] : 0u;
+#pragma unroll
+            for (int p = 0; p < PT; ++p) {
+                if ((live >> p) & 1u) {
+                    const uint32_t v = in[p] ? (val[p] & keep) : 0u;
                     const uint32_t inc = (v & 1u) | ((v & 2u) << 15);
                     acc1[p] += inc;
                     acc2[p] += ton ? inc : 0u;
@@ -230,6 +284,8 @@ struct Sums6 {
 template <int PT, int LAYOUT, bool TRI, bool SOK>
 __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t by) {
     const Tile t = tile_of<PT>(a, bx, by);
+    const uint32_t live = live_mask<PT>(a, t, bx);
+    if (live == 0u) return;  // every sample of this tile falls outside the source
     float mx[PT], my[PT], mz[PT], ax[PT], ay[PT], az[PT];
     column_terms<PT>(a, t, mx, my, mz, ax, ay, az);
     Sums6 acc[PT];
@@ -250,49 +306,83 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
             const uint32_t tv = a.tgt[tofs];
             const uint32_t tv2 = tv * tv;
             const float fk = (float)k;
+            if (TRI) {
+                // all PT samples: clamped coordinates (exact where inside), every
+                // load issued before any use, then predicated sums
+                float fxa[PT], fya[PT], fza[PT];
+                uint32_t base[PT], ddx[PT], ddy[PT], ddz[PT];
+                bool in[PT];
 #pragma unroll
-            for (int p = 0; p < PT; ++p) {
-                if (p < t.npg) {
+                for (int p = 0; p < PT; ++p) {
                     const float ux = fmaf(ax[p], fk, mx[p]);
                     const float uy = fmaf(ay[p], fk, my[p]);
                     const float uz = fmaf(az[p], fk, mz[p]);
-                    uint32_t sfx;
-                    if (TRI) {
-                        if (!(ux >= 0.0f && ux <= ex && uy >= 0.0f && uy <= ey && uz >= 0.0f && uz <= ez))
-                            continue;
-                        const float flx = floorf(ux), fly = floorf(uy), flz = floorf(uz);
-                        const uint32_t ix = (uint32_t)flx, iy = (uint32_t)fly, iz = (uint32_t)flz;
-                        const float fx = ux - flx, fy = uy - fly, fz = uz - flz;
-                        const uint32_t base = ix + sn0 * iy + sn01 * iz;
-                        if (SOK && a.src_ok[base] == 0) continue;
-                        const uint32_t dx = ix < (uint32_t)(a.sn0 - 1) ? 1u : 0u;
-                        const uint32_t dy = iy < (uint32_t)(a.sn1 - 1) ? sn0 : 0u;
-                        const uint32_t dz = iz < (uint32_t)(a.sn2 - 1) ? sn01 : 0u;
-                        float v[8];
-                        corners<LAYOUT>(a.src_packed, base, dx, dy, dz, v);
-                        const float x00 = fmaf(fx, v[1] - v[0], v[0]);
-                        const float x10 = fmaf(fx, v[3] - v[2], v[2]);
-                        const float x01 = fmaf(fx, v[5] - v[4], v[4]);
-                        const float x11 = fmaf(fx, v[7] - v[6], v[6]);
-                        const float y0 = fmaf(fy, x10 - x00, x00);
-                        const float y1 = fmaf(fy, x11 - x01, x01);
-                        const float sv = fmaf(fz, y1 - y0, y0);
-                        sfx = (uint32_t)(sv * 256.0f + 0.5f);
-                    } else {
+                    in[p] = ux >= 0.0f && ux <= ex && uy >= 0.0f && uy <= ey && uz >= 0.0f && uz <= ez;
+                    const float cx = fminf(fmaxf(ux, 0.0f), ex);
+                    const float cy = fminf(fmaxf(uy, 0.0f), ey);
+                    const float cz = fminf(fmaxf(uz, 0.0f), ez);
+                    const float flx = floorf(cx), fly = floorf(cy), flz = floorf(cz);
+                    const uint32_t ix = (uint32_t)flx, iy = (uint32_t)fly, iz = (uint32_t)flz;
+                    fxa[p] = cx - flx;
+                    fya[p] = cy - fly;
+                    fza[p] = cz - flz;
+                    base[p] = ix + sn0 * iy + sn01 * iz;
+                    ddx[p] = ix < (uint32_t)(a.sn0 - 1) ? 1u : 0u;
+                    ddy[p] = iy < (uint32_t)(a.sn1 - 1) ? sn0 : 0u;
+                    ddz[p] = iz < (uint32_t)(a.sn2 - 1) ? sn01 : 0u;
+                }
+                uint32_t okv[PT];
+                float v[PT][8];
+#pragma unroll
+                for (int p = 0; p < PT; ++p) {
+                    if ((live >> p) & 1u) {
+                        okv[p] = SOK ? (uint32_t)a.src_ok[base[p]] : 1u;
+                        corners<LAYOUT>(a.src_packed, base[p], ddx[p], ddy[p], ddz[p], v[p]);
+                    }
+                }
+#pragma unroll
+                for (int p = 0; p < PT; ++p) {
+                    if ((live >> p) & 1u) {
+                        const float x00 = fmaf(fxa[p], v[p][1] - v[p][0], v[p][0]);
+                        const float x10 = fmaf(fxa[p], v[p][3] - v[p][2], v[p][2]);
+                        const float x01 = fmaf(fxa[p], v[p][5] - v[p][4], v[p][4]);
+                        const float x11 = fmaf(fxa[p], v[p][7] - v[p][6], v[p][6]);
+                        const float y0 = fmaf(fya[p], x10 - x00, x00);
+                        const float y1 = fmaf(fya[p], x11 - x01, x01);
+                        const float sv = fmaf(fza[p], y1 - y0, y0);
+                        // s * 256 is exact, so one fused step equals the multiply-add
+                        const uint32_t sfx0 = (uint32_t)fmaf(sv, 256.0f, 0.5f);
+                        const bool valid = in[p] && okv[p] != 0u;
+                        const uint32_t sfx = valid ? sfx0 : 0u;
+                        acc[p].n += valid ? 1u : 0u;
+                        acc[p].s += sfx;
+                        acc[p].t += valid ? tv : 0u;
+                        acc[p].ss += (unsigned long long)sfx * sfx;
+                        acc[p].tt += valid ? tv2 : 0u;
+                        acc[p].st += sfx * tv;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int p = 0; p < PT; ++p) {
+                    if ((live >> p) & 1u) {
+                        const float ux = fmaf(ax[p], fk, mx[p]);
+                        const float uy = fmaf(ay[p], fk, my[p]);
+                        const float uz = fmaf(az[p], fk, mz[p]);
                         const int ix = (int)floorf(ux), iy = (int)floorf(uy), iz = (int)floorf(uz);
                         if (!((uint32_t)ix < (uint32_t)a.sn0 && (uint32_t)iy < (uint32_t)a.sn1 &&
                               (uint32_t)iz < (uint32_t)a.sn2))
                             continue;
                         const uint32_t m = (uint32_t)ix + sn0 * (uint32_t)iy + sn01 * (uint32_t)iz;
                         if (SOK && a.src_ok[m] == 0) continue;
-                        sfx = (uint32_t)a.src[m] << 8;
+                        const uint32_t sfx = (uint32_t)a.src[m] << 8;
+                        acc[p].n += 1u;
+                        acc[p].s += sfx;
+                        acc[p].t += tv;
+                        acc[p].ss += (unsigned long long)sfx * sfx;
+                        acc[p].tt += tv2;
+                        acc[p].st += sfx * tv;
                     }
-                    acc[p].n += 1u;
-                    acc[p].s += sfx;
-                    acc[p].t += tv;
-                    acc[p].ss += (unsigned long long)sfx * sfx;
-                    acc[p].tt += tv2;
-                    acc[p].st += sfx * tv;
                 }
             }
         }
@@ -406,8 +496,24 @@ KArgs make_args(const ScoreLaunch &L, int pt, int *nz_chunks) {
     a.np = L.np;
     a.tiles_x = (L.tn[0] + kTX - 1) / kTX;
     a.tiles_y = (L.tn[1] + kTY - 1) / kTY;
-    const int chunks = (L.tn[2] + kZChunkMax - 1) / kZChunkMax;
+    const int zc = L.zchunk > 0 ? std::min(L.zchunk, kZChunkMax) : kZChunkMax;
+    const int chunks = (L.tn[2] + zc - 1) / zc;
     a.zchunk = (L.tn[2] + chunks - 1) / chunks;
+    for (int d = 0; d < 3; ++d) {
+        if (L.mode == kModeImageTrilinear) {
+            // inside iff 0 <= u <= n - 1
+            a.cull_lo[d] = 0.0f;
+            a.cull_hi[d] = (float)(L.sn[d] - 1);
+        } else if (L.mode == kModeMask && L.cull_box) {
+            // only samples landing in the source mask's bounding box add to a, c
+            a.cull_lo[d] = (float)L.box_lo[d];
+            a.cull_hi[d] = (float)(L.box_hi[d] + 1);
+        } else {
+            // nearest (words carry +0.5): inside iff 0 <= u < n
+            a.cull_lo[d] = 0.0f;
+            a.cull_hi[d] = (float)L.sn[d];
+        }
+    }
     *nz_chunks = chunks;
     (void)pt;
     return a;

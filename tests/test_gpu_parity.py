@@ -283,16 +283,18 @@ def test_tuning_invariance(smc, orc):
     want = _oracle_sums(orc, orc.Volume(pair["src"], fov=pair["src_fov"]), orc.Volume(pair["tgt"]), x, "trilinear")
     for layout in ("raw", "pairx", "quadxy", "oct"):
         for pt in (4, 8, 16):
-            r.tune(layout, pt)
-            assert r.tuning() == dict(layout=smc.LAYOUTS[layout], particles_per_group=pt)
-            assert np.array_equal(r.evaluate(x), want), (layout, pt)
+            for depth in (7, 32, 256):
+                r.tune(layout, pt, depth)
+                assert r.tuning() == dict(layout=smc.LAYOUTS[layout], particles_per_group=pt, tile_depth=depth)
+                assert np.array_equal(r.evaluate(x), want), (layout, pt, depth)
     mpair = synth.shell_pair(seed=3, side=40)
     m = _reg(smc, mpair, config.default_params("dice", 21, 2, 15.0, 5.0))
     xm = _random_states(21, 15, 5, 9)
     wm = _oracle_sums(orc, orc.Volume(mpair["src"]), orc.Volume(mpair["tgt"]), xm, "mask")
     for pt in (4, 8, 16):
-        m.tune(None, pt)
-        assert np.array_equal(m.evaluate(xm), wm), pt
+        for depth in (5, 64):
+            m.tune(None, pt, depth)
+            assert np.array_equal(m.evaluate(xm), wm), (pt, depth)
     with pytest.raises(smc.SmcError):
         m.tune(None, 5)
 
