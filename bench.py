@@ -77,7 +77,21 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-time-to-dice", action="store_true")
     ap.add_argument("--ttd-pairs", type=int, default=2)
+    ap.add_argument("--tuning", default=None,
+                    help="layout,particles_per_group,tile_depth instead of autotuning (e.g. 3,4,32)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of 256 MiB (three times), to scale HBM byte counters")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        torch.cuda.set_device(0)
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b = a.clone()
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel(), "copies": 3, "checksum": int(b[::4096].sum().item())}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the registration path "
               f"runs on a single MI355X, see DESIGN.md for how it would shard)", file=sys.stderr)
@@ -109,6 +123,13 @@ def main():
     stream = torch.cuda.current_stream()
     reg = binding.Registration(src, tgt, prm, src_fov=fov)
     src_vol = binding.volume(src)
+    if args.tuning:
+        lay, ppg, depth = (int(v) for v in args.tuning.split(","))
+        reg.tune(lay, ppg, depth)
+        tuning = reg.tuning()
+    else:
+        tuning = reg.autotune(reps=2)
+    log(f"tuning: {tuning}")
 
     def step(s):
         reg.reset(1000 + s)
@@ -155,7 +176,8 @@ def main():
         "config": {"workload": f"speckle160: 160^3 u8 speckle images, 60 deg apical-cone source FOV, "
                                f"N={N} particles, K={K} iterations, {args.score.upper()}, trilinear; "
                                f"one step = one full registration + warp_apply",
-                   "particles": N, "iterations": K, "target_voxels": V, "score": args.score},
+                   "particles": N, "iterations": K, "target_voxels": V, "score": args.score,
+                   "tuning": {k: tuning[k] for k in ("layout", "particles_per_group", "tile_depth")}},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": None,
                      "kernel": "k_score_image (warp-and-score, trilinear)",

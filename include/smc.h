@@ -155,6 +155,14 @@ smc_status smc_set_state(smc_ctx *ctx, const void *buf, size_t len);
 smc_status smc_set_tuning(smc_ctx *ctx, int32_t layout, int32_t particles_per_group, int32_t tile_depth);
 smc_status smc_get_tuning(smc_ctx *ctx, int32_t *layout, int32_t *particles_per_group, int32_t *tile_depth);
 
+/* Autotuner: time every candidate tuning (layouts for trilinear images;
+ * particles per group 4 / 8; tile depths) on this context's own volumes and
+ * current particles with HIP events (reps launches each, on a scratch sum
+ * buffer), and apply the fastest.  Results are cached per problem shape for
+ * the life of the process.  best_ms (may be NULL) receives the fastest
+ * launch time.  Syncs. */
+smc_status smc_autotune(smc_ctx *ctx, uint32_t reps, double *best_ms);
+
 /* Kernel timing.  With enable != 0 every warp-and-score launch and every
  * filter launch of this context is bracketed by HIP events recorded on the
  * context's stream.  smc_profile_read syncs, returns the summed durations
@@ -235,6 +243,10 @@ smc_status smc_batch_init(smc_batch **out, uint32_t n_pairs, const smc_volume *s
 smc_status smc_batch_set_seeds(smc_batch *b, const uint64_t *seeds);
 /* Run every pair's full registration (one graph launch).  Async. */
 smc_status smc_batch_run(smc_batch *b);
+/* Autotune the largest pair of each class (masks, trilinear images), apply
+ * the result to every pair of that class and re-plan the batch (the graph is
+ * recaptured at the next run).  Syncs. */
+smc_status smc_batch_autotune(smc_batch *b, uint32_t reps);
 /* The context of pair i, for smc_estimate / smc_get_particles / smc_trace
  * (do not step or destroy it); NULL if i is out of range. */
 smc_ctx *smc_batch_pair(smc_batch *b, uint32_t i);

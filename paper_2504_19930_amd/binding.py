@@ -29,7 +29,7 @@ EXPORTS = ("smc_init", "smc_reset", "smc_step", "smc_estimate", "smc_get_particl
            "smc_set_tuning", "smc_get_tuning", "smc_batch_init", "smc_batch_set_seeds", "smc_batch_run",
            "smc_batch_pair", "smc_batch_destroy", "smc_cnn_create", "smc_cnn_set_params", "smc_cnn_get_params",
            "smc_cnn_input", "smc_cnn_read_input", "smc_cnn_forward", "smc_cnn_backward", "smc_cnn_step", "smc_cnn_destroy",
-           "smc_set_proposal", "smc_exhaustive")
+           "smc_set_proposal", "smc_exhaustive", "smc_autotune", "smc_batch_autotune")
 
 
 class SmcError(RuntimeError):
@@ -92,6 +92,8 @@ def lib():
             "smc_cnn_step": [vp, C.c_float],
             "smc_set_proposal": [vp, vp, vp],
             "smc_exhaustive": [vp, vp, vp, vp, vp, vp, vp],
+            "smc_autotune": [vp, u32, vp],
+            "smc_batch_autotune": [vp, u32],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -339,6 +341,11 @@ class Registration:
     def set_proposal(self, mean=None, logvar=None):
         smc_set_proposal(self.ctx, mean, logvar)
 
+    def autotune(self, reps=3):
+        ms = C.c_double()
+        _check(lib().smc_autotune(self.ctx, int(reps), C.cast(C.byref(ms), C.c_void_p)))
+        return dict(self.tuning(), ms=ms.value)
+
     def tune(self, layout=None, particles_per_group=None, tile_depth=None):
         smc_set_tuning(self.ctx, layout, particles_per_group, tile_depth)
 
@@ -392,6 +399,9 @@ class Batch:
 
     def run(self):
         _check(lib().smc_batch_run(self.b))
+
+    def autotune(self, reps=3):
+        _check(lib().smc_batch_autotune(self.b, int(reps)))
 
     def pair(self, i):
         return C.c_void_p(lib().smc_batch_pair(self.b, int(i)))

@@ -9,6 +9,9 @@
 #include <limits.h>
 
 #include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,8 +26,9 @@ namespace {
 thread_local std::string g_err;
 
 // Launch defaults (see smc_set_tuning).
-constexpr int kDefaultLayout = kLayoutRaw;
-constexpr int kDefaultPT = 8;
+// (measured on MI355X: packed octets, 4 particles per workgroup; see smc_autotune)
+constexpr int kDefaultLayout = kLayoutOct;
+constexpr int kDefaultPT = 4;
 constexpr int kDefaultZChunk = 32;
 
 smc_status fail(smc_status st, const char *fmt, ...) {
@@ -657,6 +661,97 @@ smc_status smc_set_tuning(smc_ctx *c, int32_t layout, int32_t pt, int32_t tile_d
     return SMC_OK;
 }
 
+namespace {
+struct TuneKey {
+    int mode;
+    int32_t sn[3], tn[3];
+    bool sok, tfov;
+    uint32_t n;
+    bool operator<(const TuneKey &o) const {
+        return std::memcmp(this, &o, sizeof(TuneKey)) < 0;
+    }
+};
+struct TuneVal {
+    int layout, pt, zchunk;
+    double ms;
+};
+std::map<TuneKey, TuneVal> &tune_cache() {
+    static std::map<TuneKey, TuneVal> m;
+    return m;
+}
+std::mutex &tune_mutex() {
+    static std::mutex m;
+    return m;
+}
+}  // namespace
+
+smc_status smc_autotune(smc_ctx *c, uint32_t reps, double *best_ms) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (reps < 1 || reps > 100) return fail(SMC_EINVAL, "reps must be in 1..100");
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    TuneKey key;
+    std::memset(&key, 0, sizeof key);
+    key.mode = c->mode;
+    for (int d = 0; d < 3; ++d) {
+        key.sn[d] = c->sn[d];
+        key.tn[d] = c->tn[d];
+    }
+    key.sok = c->src_ok != nullptr;
+    key.tfov = c->tgt_fov != nullptr;
+    key.n = c->f.n;
+    {
+        std::lock_guard<std::mutex> g(tune_mutex());
+        auto it = tune_cache().find(key);
+        if (it != tune_cache().end()) {
+            if ((st = smc_set_tuning(c, it->second.layout, it->second.pt, it->second.zchunk)) != SMC_OK) return st;
+            if (best_ms) *best_ms = it->second.ms;
+            return SMC_OK;
+        }
+    }
+    const uint32_t np = c->f.n + 1;
+    if ((st = ensure_eval(c, np)) != SMC_OK) return c->mark(st);
+    std::vector<int> layouts = {kLayoutRaw};
+    if (c->mode == kModeImageTrilinear) layouts = {kLayoutRaw, kLayoutPairX, kLayoutQuadXY, kLayoutOct};
+    const int depths_img[] = {32, 256}, depths_mask[] = {16, 32, 256};
+    const int *depths = c->mode == kModeMask ? depths_mask : depths_img;
+    const int nd = c->mode == kModeMask ? 3 : 2;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    TuneVal best{c->layout, c->pt, c->zchunk, 1e30};
+    smc_status result = SMC_OK;
+    for (int lay : layouts)
+        for (int pt : {4, 8})
+            for (int q = 0; q < nd && result == SMC_OK; ++q) {
+                if ((result = smc_set_tuning(c, lay, pt, depths[q])) != SMC_OK) break;
+                const ScoreLaunch L = c->score_launch(c->f.words, c->s_eval, 0, np, true);
+                double tot = 0.0;
+                for (uint32_t r = 0; r <= reps && result == SMC_OK; ++r) {
+                    float ms = 0.0f;
+                    if (launch_fill_u64(c->s_eval, 6ull * np, c->stream) != hipSuccess ||
+                        hipEventRecord(e0, c->stream) != hipSuccess || launch_score(L, c->stream) != hipSuccess ||
+                        hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                        result = fail(SMC_EDEVICE, "autotune launch failed");
+                    if (r > 0) tot += ms;  // the first launch warms caches
+                }
+                const double avg = tot / reps;
+                if (avg < best.ms) best = TuneVal{lay, pt, depths[q], avg};
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != SMC_OK) return c->mark(result);
+    if ((st = smc_set_tuning(c, best.layout, best.pt, best.zchunk)) != SMC_OK) return st;
+    {
+        std::lock_guard<std::mutex> g(tune_mutex());
+        tune_cache()[key] = best;
+    }
+    if (best_ms) *best_ms = best.ms;
+    return SMC_OK;
+}
+
 smc_status smc_get_tuning(smc_ctx *c, int32_t *layout, int32_t *pt, int32_t *tile_depth) {
     if (!c) return fail(SMC_EINVAL, "ctx is NULL");
     if (layout) *layout = c->layout;
@@ -962,6 +1057,36 @@ smc_status smc_batch_run(smc_batch *b) {
     HIP_TRY(hipEventRecord(b->ev_out, b->stream));
     HIP_TRY(hipStreamWaitEvent(b->caller, b->ev_out, 0));
     for (smc_ctx *c : b->pairs) c->k_done = c->f.n_iters;
+    return SMC_OK;
+}
+
+smc_status smc_batch_autotune(smc_batch *b, uint32_t reps) {
+    if (!b) return fail(SMC_EINVAL, "batch is NULL");
+    smc_status st;
+    for (int q = 0; q < 2; ++q) {
+        auto &C = b->cls[q];
+        if (C.members.empty()) continue;
+        uint32_t big = C.members[0];
+        double work = 0.0;
+        for (uint32_t i : C.members) {
+            smc_ctx *c = b->pairs[i];
+            const double w = (double)c->tn[0] * c->tn[1] * c->tn[2] * (double)(c->f.n + 1);
+            if (w > work) {
+                work = w;
+                big = i;
+            }
+        }
+        smc_ctx *c0 = b->pairs[big];
+        if ((st = smc_autotune(c0, reps, nullptr)) != SMC_OK) return st;
+        for (uint32_t i : C.members)
+            if ((st = smc_set_tuning(b->pairs[i], c0->layout, c0->pt, c0->zchunk)) != SMC_OK) return st;
+        if ((st = plan_class(b, C, q == 0 ? kModeMask : kModeImageTrilinear)) != SMC_OK) return st;
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
     return SMC_OK;
 }
 

@@ -64,20 +64,29 @@ def _gen(seed):
     return p["src"], p["tgt"], p["src_mask"], p["tgt_mask"], p["spacing"]
 
 
-def make_training_set(n_pairs: int, seed0: int = 1_000_000, workers: int = 16):
+def make_training_set(n_pairs: int, seed0: int = 1_000_000, workers: int = 16, log=None):
     """Training pairs on the network's 64^3 grid (CPU, process pool)."""
-    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
     seeds = [seed0 + i for i in range(n_pairs)]
+    shape = (n_pairs, 64, 64, 64)
+    src, tgt = np.empty(shape, np.uint8), np.empty(shape, np.uint8)
+    smask, tmask = np.empty(shape, np.uint8), np.empty(shape, np.uint8)
+    spacing = None
+
+    def put(i, r):
+        nonlocal spacing
+        src[i], tgt[i], smask[i], tmask[i], spacing = r
+        if log and (i + 1) % 1000 == 0:
+            log(f"generated {i + 1}/{n_pairs}")
+
     if workers > 1:
-        with ProcessPoolExecutor(workers) as ex:
-            rows = list(ex.map(_gen, seeds, chunksize=64))
+        with mp.get_context("fork").Pool(workers) as pool:
+            for i, r in enumerate(pool.imap(_gen, seeds, chunksize=16)):
+                put(i, r)
     else:
-        rows = [_gen(s) for s in seeds]
-    src = np.stack([r[0] for r in rows])
-    tgt = np.stack([r[1] for r in rows])
-    smask = np.stack([r[2] for r in rows])
-    tmask = np.stack([r[3] for r in rows])
-    return dict(src=src, tgt=tgt, src_mask=smask, tgt_mask=tmask, spacing=rows[0][4])
+        for i, sd in enumerate(seeds):
+            put(i, _gen(sd))
+    return dict(src=src, tgt=tgt, src_mask=smask, tgt_mask=tmask, spacing=spacing)
 
 
 def label_with_smc(data, n_particles=256, n_iters=15, batch_pairs=256, seed=7, log=None):
@@ -274,11 +283,12 @@ def main(argv=None):
     e.add_argument("--var-scale", type=float, default=4.0)
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
-    _torch().cuda.set_device(0)
     if args.cmd == "train":
         t0 = time.perf_counter()
-        data = make_training_set(args.pairs, workers=args.workers)
+        # the worker pool forks before anything touches the GPU
+        data = make_training_set(args.pairs, workers=args.workers, log=log)
         log(f"generated {args.pairs} pairs in {time.perf_counter() - t0:.1f}s")
+        _torch().cuda.set_device(0)
         mean, var = label_with_smc(data, log=log)
         log(f"labelled in {time.perf_counter() - t0:.1f}s")
         params, hist = train(data, mean, var, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
@@ -287,6 +297,7 @@ def main(argv=None):
         log(f"saved {args.out} after {time.perf_counter() - t0:.1f}s")
     else:
         import synth
+        _torch().cuda.set_device(0)
         params = load_weights(args.weights)
         rows = []
         for i in range(args.pairs):

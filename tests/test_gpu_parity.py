@@ -359,3 +359,19 @@ def test_exhaustive_search_matches_oracle_grid(smc, orc):
     ref = pb.score(prm, grid)
     assert np.array_equal(got["scores"], ref)
     assert got["score"] == ref.max()
+
+
+def test_autotune_keeps_results(smc, orc):
+    pair = synth.speckle_pair(side=48, seed=19, trans=4.0)
+    prm = config.default_params("ncc", 64, 2, 20.0, 4.0)
+    r = _reg(smc, pair, prm, src_fov=pair["src_fov"])
+    t = r.autotune(reps=2)
+    assert t["layout"] in (0, 1, 2, 3) and t["particles_per_group"] in (4, 8) and t["ms"] > 0
+    x = _random_states(20, 20, 4, 23)
+    want = _oracle_sums(orc, orc.Volume(pair["src"], fov=pair["src_fov"]), orc.Volume(pair["tgt"]), x, "trilinear")
+    assert np.array_equal(r.evaluate(x), want)
+    # cached: a second context with the same shapes gets the same choice without timing
+    r2 = _reg(smc, pair, prm, src_fov=pair["src_fov"])
+    t2 = r2.autotune(reps=2)
+    assert {k: t2[k] for k in ("layout", "particles_per_group", "tile_depth")} == \
+        {k: t[k] for k in ("layout", "particles_per_group", "tile_depth")}
