@@ -119,6 +119,8 @@ struct smc_ctx {
     int layout = kDefaultLayout, pt = kDefaultPT, zchunk = kDefaultZChunk;
     int32_t box_lo[3] = {1, 1, 1}, box_hi[3] = {-1, -1, -1};  // source mask bounding box (empty)
     void *packed[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint64_t sentinel[4] = {0, 0, 0, 0};  // per packed layout: value marking elements outside the source FOV
+    bool has_sentinel[4] = {false, false, false, false};
     FilterState f{};
     uint32_t k_done = 0;
     smc_status sticky = SMC_OK;
@@ -171,6 +173,8 @@ struct smc_ctx {
         }
         L.layout = mode == kModeImageTrilinear ? layout : kLayoutRaw;
         L.src_packed = mode == kModeImageTrilinear ? packed[L.layout] : nullptr;
+        L.has_sentinel = mode == kModeImageTrilinear && has_sentinel[L.layout];
+        L.sentinel = sentinel[L.layout];
         L.pt = pt;
         L.words = words;
         L.sums = sums;
@@ -225,6 +229,57 @@ hipError_t timed(smc_ctx *c, std::vector<std::pair<hipEvent_t, hipEvent_t>> &log
     if (e == hipSuccess) e = hipEventRecord(b, c->stream);
     log.emplace_back(a, b);
     return e;
+}
+
+uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// Allocate and fill a packed trilinear layout of the source.  With a source
+// FOV, find a value no in-FOV element takes and store it in every element
+// that touches a voxel outside the FOV (then samples need no separate
+// validity gather); if none is free, pack plainly and keep the gather.
+smc_status prepare_layout(smc_ctx *c, int layout) {
+    if (c->mode != kModeImageTrilinear || layout == kLayoutRaw || c->packed[layout]) return SMC_OK;
+    const int64_t vs = (int64_t)c->sn[0] * c->sn[1] * c->sn[2];
+    smc_status st;
+    if ((st = c->alloc((uint8_t **)&c->packed[layout], vs * packed_bytes_per_voxel(layout))) != SMC_OK) return st;
+    uint64_t sent = 0;
+    bool ok = false;
+    if (c->src_fov) {
+        const int n_cand = layout == kLayoutPairX ? 0 : 64;
+        const size_t n_counts = layout == kLayoutPairX ? 65536 : 64;
+        std::vector<uint64_t> cand(64);
+        for (int q = 0; q < 64; ++q) cand[q] = splitmix64((uint64_t)q + 1);
+        uint64_t *dcand = nullptr;
+        unsigned long long *dcounts = nullptr;
+        std::vector<unsigned long long> counts(n_counts);
+        hipError_t e = hipMalloc(&dcand, 8 * 64);
+        if (e == hipSuccess) e = hipMalloc(&dcounts, 8 * n_counts);
+        if (e == hipSuccess) e = hipMemcpyAsync(dcand, cand.data(), 8 * 64, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = launch_fill_u64(dcounts, n_counts, c->stream);
+        if (e == hipSuccess)
+            e = launch_count_elements(c->src, c->src_fov, c->sn, layout, dcand, n_cand, dcounts, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(counts.data(), dcounts, 8 * n_counts, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (dcand) (void)hipFree(dcand);
+        if (dcounts) (void)hipFree(dcounts);
+        if (e != hipSuccess) return fail(SMC_EDEVICE, "sentinel search failed: %s", hipGetErrorString(e));
+        for (size_t q = 0; q < n_counts && !ok; ++q)
+            if (counts[q] == 0) {
+                sent = layout == kLayoutPairX ? (uint64_t)q : cand[q];
+                ok = true;
+            }
+    }
+    HIP_TRY(launch_pack_source(c->src, ok ? c->src_fov : nullptr, c->sn, layout, sent, c->packed[layout],
+                               c->stream));
+    c->sentinel[layout] = sent;
+    c->has_sentinel[layout] = ok;
+    return SMC_OK;
 }
 
 smc_status launch_prior(smc_ctx *c) {
@@ -315,12 +370,7 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
         }
     }
 
-    if (c->mode == kModeImageTrilinear && c->layout != kLayoutRaw) {
-        if ((st = c->alloc((uint8_t **)&c->packed[c->layout], vs * packed_bytes_per_voxel(c->layout))) != SMC_OK)
-            return bail(st);
-        if (launch_pack_source(src->data, c->sn, c->layout, c->packed[c->layout], c->stream) != hipSuccess)
-            return bail(fail(SMC_EDEVICE, "source packing launch failed"));
-    }
+    if ((st = prepare_layout(c, c->layout)) != SMC_OK) return bail(st);
 
     if (c->mode == kModeMask) {
         int32_t *dbox = nullptr;
@@ -648,12 +698,7 @@ smc_status smc_set_tuning(smc_ctx *c, int32_t layout, int32_t pt, int32_t tile_d
     if ((st = c->check_sticky()) != SMC_OK) return st;
     if ((st = set_device(c)) != SMC_OK) return c->mark(st);
     if (layout >= 0) {
-        if (c->mode == kModeImageTrilinear && layout != kLayoutRaw && !c->packed[layout]) {
-            const int64_t vs = (int64_t)c->sn[0] * c->sn[1] * c->sn[2];
-            if ((st = c->alloc((uint8_t **)&c->packed[layout], vs * packed_bytes_per_voxel(layout))) != SMC_OK)
-                return st;
-            HIP_TRY(launch_pack_source(c->src, c->sn, layout, c->packed[layout], c->stream));
-        }
+        if ((st = prepare_layout(c, layout)) != SMC_OK) return c->mark(st);
         c->layout = layout;
     }
     if (pt >= 0) c->pt = pt;

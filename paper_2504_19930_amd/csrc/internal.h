@@ -20,6 +20,8 @@ struct ScoreLaunch {
     int mode;
     const uint8_t *src;       // mask: prepared bits; image: intensities
     const void *src_packed;   // trilinear: source in `layout` (nullptr = raw bytes)
+    bool has_sentinel;        // packed elements equal to `sentinel` mark samples outside the source FOV
+    uint64_t sentinel;
     int layout;               // SourceLayout
     int pt;                   // particles per workgroup: 4, 8 or 16
     int zchunk;               // target z-extent of a tile (0 = up to 256)
@@ -40,7 +42,14 @@ hipError_t launch_score(const ScoreLaunch &L, hipStream_t s);
 void score_grid(const ScoreLaunch &L, dim3 *grid, dim3 *block);
 bool score_pt_supported(int pt);
 // Pack a source volume into `layout` (edge corners repeat the last voxel).
-hipError_t launch_pack_source(const uint8_t *vol, const int32_t n[3], int layout, void *out, hipStream_t s);
+// With fov, elements touching a voxel outside it hold `sentinel` instead.
+hipError_t launch_pack_source(const uint8_t *vol, const uint8_t *fov, const int32_t n[3], int layout,
+                              uint64_t sentinel, void *out, hipStream_t s);
+// Over the elements of `layout` that lie inside the fov, count those equal to
+// each candidate (truncated to the element width) -- or, for x-pairs with
+// n_cand == 0, a 65536-bin histogram of all element values.
+hipError_t launch_count_elements(const uint8_t *vol, const uint8_t *fov, const int32_t n[3], int layout,
+                                 const uint64_t *cand, int n_cand, unsigned long long *counts, hipStream_t s);
 size_t packed_bytes_per_voxel(int layout);
 
 // Batched warp-and-score: one persistent launch over the work items of many

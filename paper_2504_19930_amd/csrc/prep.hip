@@ -69,27 +69,72 @@ __global__ __launch_bounds__(256) void k_volume_sums(const uint8_t *vol, const u
 }
 
 // Trilinear source layouts: per base voxel the corner bytes the kernel needs,
-// with corners past the last voxel repeating it (see score.hip).
-__global__ void k_pack_source(const uint8_t *vol, int32_t nx, int32_t ny, int32_t nz, int layout, void *out) {
+// with corners past the last voxel repeating it (see score.hip).  The
+// element of voxel q and its FOV validity (all voxels it covers inside):
+//   pairx  (v[x], v[x+1]) of one row;  quadxy  the 2x2 of one slice;
+//   oct    the 2x2x2 of the trilinear cell.
+// A trilinear sample is inside the FOV iff every element it reads is, so an
+// invalid element may hold a sentinel value that no valid element takes.
+struct Elem {
+    uint64_t value;
+    bool valid;
+};
+
+__device__ __forceinline__ Elem element(const uint8_t *vol, const uint8_t *fov, int32_t nx, int32_t ny, int32_t nz,
+                                        int layout, int64_t q) {
+    const int32_t i = (int32_t)(q % nx);
+    const int32_t j = (int32_t)((q / nx) % ny);
+    const int32_t k = (int32_t)(q / ((int64_t)nx * ny));
+    const int64_t dx = i + 1 < nx ? 1 : 0;
+    const int64_t dy = j + 1 < ny ? nx : 0;
+    const int64_t dz = k + 1 < nz ? (int64_t)nx * ny : 0;
+    Elem e;
+    if (layout == kLayoutPairX) {
+        e.value = (uint64_t)vol[q] | ((uint64_t)vol[q + dx] << 8);
+        e.valid = !fov || (fov[q] && fov[q + dx]);
+        return e;
+    }
+    const uint32_t q0 = (uint32_t)vol[q] | ((uint32_t)vol[q + dx] << 8) | ((uint32_t)vol[q + dy] << 16) |
+                        ((uint32_t)vol[q + dy + dx] << 24);
+    const bool v0 = !fov || (fov[q] && fov[q + dx] && fov[q + dy] && fov[q + dy + dx]);
+    if (layout == kLayoutQuadXY) {
+        e.value = q0;
+        e.valid = v0;
+        return e;
+    }
+    const int64_t r = q + dz;
+    const uint32_t q1 = (uint32_t)vol[r] | ((uint32_t)vol[r + dx] << 8) | ((uint32_t)vol[r + dy] << 16) |
+                        ((uint32_t)vol[r + dy + dx] << 24);
+    const bool v1 = !fov || (fov[r] && fov[r + dx] && fov[r + dy] && fov[r + dy + dx]);
+    e.value = (uint64_t)q0 | ((uint64_t)q1 << 32);
+    e.valid = v0 && v1;
+    return e;
+}
+
+__global__ void k_pack_source(const uint8_t *vol, const uint8_t *fov, int32_t nx, int32_t ny, int32_t nz,
+                              int layout, uint64_t sentinel, void *out) {
     const int64_t n = (int64_t)nx * ny * nz;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t i = (int32_t)(q % nx);
-        const int32_t j = (int32_t)((q / nx) % ny);
-        const int32_t k = (int32_t)(q / ((int64_t)nx * ny));
-        const int64_t dx = i + 1 < nx ? 1 : 0;
-        const int64_t dy = j + 1 < ny ? nx : 0;
-        const int64_t dz = k + 1 < nz ? (int64_t)nx * ny : 0;
-        const uint32_t q0 = (uint32_t)vol[q] | ((uint32_t)vol[q + dx] << 8) | ((uint32_t)vol[q + dy] << 16) |
-                            ((uint32_t)vol[q + dy + dx] << 24);
-        if (layout == kLayoutPairX) {
-            ((uint16_t *)out)[q] = (uint16_t)(q0 & 0xFFFFu);
-        } else if (layout == kLayoutQuadXY) {
-            ((uint32_t *)out)[q] = q0;
+        const Elem e = element(vol, fov, nx, ny, nz, layout, q);
+        const uint64_t v = e.valid ? e.value : sentinel;
+        if (layout == kLayoutPairX) ((uint16_t *)out)[q] = (uint16_t)v;
+        else if (layout == kLayoutQuadXY) ((uint32_t *)out)[q] = (uint32_t)v;
+        else ((uint2 *)out)[q] = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+    }
+}
+
+__global__ void k_count_elements(const uint8_t *vol, const uint8_t *fov, int32_t nx, int32_t ny, int32_t nz,
+                                 int layout, const uint64_t *cand, int n_cand, unsigned long long *counts) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    const uint64_t mask = layout == kLayoutPairX ? 0xFFFFull : (layout == kLayoutQuadXY ? 0xFFFFFFFFull : ~0ull);
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const Elem e = element(vol, fov, nx, ny, nz, layout, q);
+        if (!e.valid) continue;
+        if (n_cand == 0) {
+            atomicAdd(counts + e.value, 1ull);
         } else {
-            const int64_t r = q + dz;
-            const uint32_t q1 = (uint32_t)vol[r] | ((uint32_t)vol[r + dx] << 8) | ((uint32_t)vol[r + dy] << 16) |
-                                ((uint32_t)vol[r + dy + dx] << 24);
-            ((uint2 *)out)[q] = make_uint2(q0, q1);
+            for (int c = 0; c < n_cand; ++c)
+                if (e.value == (cand[c] & mask)) atomicAdd(counts + c, 1ull);
         }
     }
 }
@@ -145,10 +190,20 @@ size_t packed_bytes_per_voxel(int layout) {
     }
 }
 
-hipError_t launch_pack_source(const uint8_t *vol, const int32_t n[3], int layout, void *out, hipStream_t s) {
+hipError_t launch_pack_source(const uint8_t *vol, const uint8_t *fov, const int32_t n[3], int layout,
+                              uint64_t sentinel, void *out, hipStream_t s) {
     if (layout == kLayoutRaw) return hipSuccess;
     const int64_t tot = (int64_t)n[0] * n[1] * n[2];
-    hipLaunchKernelGGL(k_pack_source, dim3(blocks_for(tot)), dim3(256), 0, s, vol, n[0], n[1], n[2], layout, out);
+    hipLaunchKernelGGL(k_pack_source, dim3(blocks_for(tot)), dim3(256), 0, s, vol, fov, n[0], n[1], n[2], layout,
+                       sentinel, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_elements(const uint8_t *vol, const uint8_t *fov, const int32_t n[3], int layout,
+                                 const uint64_t *cand, int n_cand, unsigned long long *counts, hipStream_t s) {
+    const int64_t tot = (int64_t)n[0] * n[1] * n[2];
+    hipLaunchKernelGGL(k_count_elements, dim3(blocks_for(tot)), dim3(256), 0, s, vol, fov, n[0], n[1], n[2], layout,
+                       cand, n_cand, counts);
     return hipGetLastError();
 }
 

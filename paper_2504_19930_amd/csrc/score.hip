@@ -40,6 +40,10 @@ struct KArgs {
     // exact culling: a particle can add to the sums of a tile only if the
     // tile's image reaches the source-coordinate box [cull_lo, cull_hi]
     float cull_lo[3], cull_hi[3];
+    // source FOV validity of a trilinear sample: 0 none, 1 gather src_ok,
+    // 2 packed elements equal to `sentinel` mark samples outside the FOV
+    int32_t vmode;
+    uint64_t sentinel;
 };
 
 // Culling margin (voxels): far above the FP32 rounding of the coordinate
@@ -228,7 +232,7 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
 //   oct    uint64 (quad of slice z, quad of slice z+1), one gather
 template <int LAYOUT>
 __device__ __forceinline__ void corners(const void *src, uint32_t base, uint32_t dx, uint32_t dy, uint32_t dz,
-                                        float v[8]) {
+                                        float v[8], uint64_t sentinel, bool &sent_ok) {
     if (LAYOUT == kLayoutRaw) {
         const uint8_t *S = (const uint8_t *)src + base;
         v[0] = (float)S[0];
@@ -239,9 +243,12 @@ __device__ __forceinline__ void corners(const void *src, uint32_t base, uint32_t
         v[5] = (float)S[dz + dx];
         v[6] = (float)S[dz + dy];
         v[7] = (float)S[dz + dy + dx];
+        sent_ok = true;
     } else if (LAYOUT == kLayoutPairX) {
         const uint16_t *S = (const uint16_t *)src + base;
         const uint32_t a = S[0], b = S[dy], c = S[dz], d = S[dz + dy];
+        const uint32_t st = (uint32_t)(sentinel & 0xFFFFu);
+        sent_ok = a != st && b != st && c != st && d != st;
         v[0] = (float)(a & 0xFFu);
         v[1] = (float)(a >> 8);
         v[2] = (float)(b & 0xFFu);
@@ -256,10 +263,13 @@ __device__ __forceinline__ void corners(const void *src, uint32_t base, uint32_t
             const uint32_t *S = (const uint32_t *)src + base;
             lo = S[0];
             hi = S[dz];
+            const uint32_t st = (uint32_t)sentinel;
+            sent_ok = lo != st && hi != st;
         } else {
             const uint2 w = ((const uint2 *)src)[base];
             lo = w.x;
             hi = w.y;
+            sent_ok = lo != (uint32_t)sentinel || hi != (uint32_t)(sentinel >> 32);
         }
         v[0] = (float)(lo & 0xFFu);
         v[1] = (float)((lo >> 8) & 0xFFu);
@@ -281,8 +291,9 @@ struct Sums6 {
 // sampled source value in units of 1/256 (exact: s_fx = floor(256 s + 0.5)).
 // TRI: trilinear (inside iff 0 <= u <= n - 1 and the eight corners in the
 // source FOV); otherwise nearest (the words carry the +0.5 shift).
-template <int PT, int LAYOUT, bool TRI, bool SOK>
+template <int PT, int LAYOUT, bool TRI, int VMODE>
 __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t by) {
+    constexpr bool SOK = VMODE == 1;
     const Tile t = tile_of<PT>(a, bx, by);
     const uint32_t live = live_mask<PT>(a, t, bx);
     if (live == 0u) return;  // every sample of this tile falls outside the source
@@ -300,15 +311,19 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
         const uint32_t sn0 = (uint32_t)a.sn0, sn01 = (uint32_t)a.sn0 * (uint32_t)a.sn1;
         const float ex = (float)(a.sn0 - 1), ey = (float)(a.sn1 - 1), ez = (float)(a.sn2 - 1);
         const bool tfov = a.tgt_fov != nullptr;
+        // the target byte of the next slice is loaded one step ahead
+        uint32_t tv_next = (t.k0 < t.k1) ? (uint32_t)a.tgt[tofs0 + plane * (size_t)t.k0] : 0u;
         for (int k = t.k0; k < t.k1; ++k) {
             const size_t tofs = tofs0 + plane * (size_t)k;
+            const uint32_t tv = tv_next;
+            if (k + 1 < t.k1) tv_next = a.tgt[tofs + plane];
             if (tfov && a.tgt_fov[tofs] == 0) continue;
-            const uint32_t tv = a.tgt[tofs];
             const uint32_t tv2 = tv * tv;
             const float fk = (float)k;
             if (TRI) {
-                // all PT samples: clamped coordinates (exact where inside), every
-                // load issued before any use, then predicated sums
+                // all PT samples: clamped coordinates (exact where inside, so every
+                // address is valid), all loads issued before any use, then sums
+                // predicated on inside && FOV-valid && particle live for this tile
                 float fxa[PT], fya[PT], fza[PT];
                 uint32_t base[PT], ddx[PT], ddy[PT], ddz[PT];
                 bool in[PT];
@@ -317,10 +332,11 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                     const float ux = fmaf(ax[p], fk, mx[p]);
                     const float uy = fmaf(ay[p], fk, my[p]);
                     const float uz = fmaf(az[p], fk, mz[p]);
-                    in[p] = ux >= 0.0f && ux <= ex && uy >= 0.0f && uy <= ey && uz >= 0.0f && uz <= ez;
-                    const float cx = fminf(fmaxf(ux, 0.0f), ex);
-                    const float cy = fminf(fmaxf(uy, 0.0f), ey);
-                    const float cz = fminf(fmaxf(uz, 0.0f), ez);
+                    in[p] = ((live >> p) & 1u) & (ux >= 0.0f) & (ux <= ex) & (uy >= 0.0f) & (uy <= ey) &
+                            (uz >= 0.0f) & (uz <= ez);
+                    const float cx = __builtin_amdgcn_fmed3f(ux, 0.0f, ex);
+                    const float cy = __builtin_amdgcn_fmed3f(uy, 0.0f, ey);
+                    const float cz = __builtin_amdgcn_fmed3f(uz, 0.0f, ez);
                     const float flx = floorf(cx), fly = floorf(cy), flz = floorf(cz);
                     const uint32_t ix = (uint32_t)flx, iy = (uint32_t)fly, iz = (uint32_t)flz;
                     fxa[p] = cx - flx;
@@ -335,32 +351,29 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                 float v[PT][8];
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
-                    if ((live >> p) & 1u) {
-                        okv[p] = SOK ? (uint32_t)a.src_ok[base[p]] : 1u;
-                        corners<LAYOUT>(a.src_packed, base[p], ddx[p], ddy[p], ddz[p], v[p]);
-                    }
+                    bool sent_ok;
+                    corners<LAYOUT>(a.src_packed, base[p], ddx[p], ddy[p], ddz[p], v[p], a.sentinel, sent_ok);
+                    okv[p] = SOK ? (uint32_t)a.src_ok[base[p]] : (VMODE == 2 ? (sent_ok ? 1u : 0u) : 1u);
                 }
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
-                    if ((live >> p) & 1u) {
-                        const float x00 = fmaf(fxa[p], v[p][1] - v[p][0], v[p][0]);
-                        const float x10 = fmaf(fxa[p], v[p][3] - v[p][2], v[p][2]);
-                        const float x01 = fmaf(fxa[p], v[p][5] - v[p][4], v[p][4]);
-                        const float x11 = fmaf(fxa[p], v[p][7] - v[p][6], v[p][6]);
-                        const float y0 = fmaf(fya[p], x10 - x00, x00);
-                        const float y1 = fmaf(fya[p], x11 - x01, x01);
-                        const float sv = fmaf(fza[p], y1 - y0, y0);
-                        // s * 256 is exact, so one fused step equals the multiply-add
-                        const uint32_t sfx0 = (uint32_t)fmaf(sv, 256.0f, 0.5f);
-                        const bool valid = in[p] && okv[p] != 0u;
-                        const uint32_t sfx = valid ? sfx0 : 0u;
-                        acc[p].n += valid ? 1u : 0u;
-                        acc[p].s += sfx;
-                        acc[p].t += valid ? tv : 0u;
-                        acc[p].ss += (unsigned long long)sfx * sfx;
-                        acc[p].tt += valid ? tv2 : 0u;
-                        acc[p].st += sfx * tv;
-                    }
+                    const float x00 = fmaf(fxa[p], v[p][1] - v[p][0], v[p][0]);
+                    const float x10 = fmaf(fxa[p], v[p][3] - v[p][2], v[p][2]);
+                    const float x01 = fmaf(fxa[p], v[p][5] - v[p][4], v[p][4]);
+                    const float x11 = fmaf(fxa[p], v[p][7] - v[p][6], v[p][6]);
+                    const float y0 = fmaf(fya[p], x10 - x00, x00);
+                    const float y1 = fmaf(fya[p], x11 - x01, x01);
+                    const float sv = fmaf(fza[p], y1 - y0, y0);
+                    // s * 256 is exact, so one fused step equals the multiply-add
+                    const uint32_t sfx0 = (uint32_t)fmaf(sv, 256.0f, 0.5f);
+                    const uint32_t valid = (in[p] ? 1u : 0u) & okv[p];
+                    const uint32_t sfx = valid ? sfx0 : 0u;
+                    acc[p].n += valid;
+                    acc[p].s += sfx;
+                    acc[p].t += valid ? tv : 0u;
+                    acc[p].ss += (unsigned long long)sfx * sfx;
+                    acc[p].tt += valid ? tv2 : 0u;
+                    acc[p].st += sfx * tv;
                 }
             } else {
 #pragma unroll
@@ -418,21 +431,41 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
     }
 }
 
-template <int PT>
-__global__ __launch_bounds__(kThreads) void k_score_mask(const KArgs a) {
-    mask_body<PT>(a, blockIdx.x, blockIdx.y);
+// XCD-aware order of a one-dimensional grid of tiles x particle groups.
+// The dispatcher hands workgroup b to XCD b % 8; XCD x is given the x-th
+// contiguous eighth of the work sequence w = tile * groups + group, so it
+// sweeps a few tiles at a time across all particle groups.  The particles
+// of one filter are clustered, so the source footprint of the tiles in
+// flight on an XCD stays within its L2 instead of every XCD streaming the
+// whole source once per particle group.
+__device__ __forceinline__ void xcd_order(uint32_t b, uint32_t total, uint32_t groups, uint32_t *bx,
+                                          uint32_t *by) {
+    const uint32_t x = b % 8u, r = b / 8u;
+    const uint32_t q = total / 8u, rem = total % 8u;
+    const uint32_t w = x * q + min(x, rem) + r;
+    *bx = w / groups;
+    *by = w - *bx * groups;
 }
 
-template <int PT, int LAYOUT, bool TRI, bool SOK>
+template <int PT>
+__global__ __launch_bounds__(kThreads) void k_score_mask(const KArgs a) {
+    uint32_t bx, by;
+    xcd_order(blockIdx.x, gridDim.x, (a.np + PT - 1) / PT, &bx, &by);
+    mask_body<PT>(a, bx, by);
+}
+
+template <int PT, int LAYOUT, bool TRI, int VMODE>
 __global__ __launch_bounds__(kThreads) void k_score_image(const KArgs a) {
-    image_body<PT, LAYOUT, TRI, SOK>(a, blockIdx.x, blockIdx.y);
+    uint32_t bx, by;
+    xcd_order(blockIdx.x, gridDim.x, (a.np + PT - 1) / PT, &bx, &by);
+    image_body<PT, LAYOUT, TRI, VMODE>(a, bx, by);
 }
 
 // ---------------------------------------------------------------- batches
 
 // Persistent warp-and-score over the work items of many pairs.  Item g of
-// pair d (offs[d] <= g < offs[d + 1]) is tile g - offs[d] mod ntiles(d) and
-// particle group (g - offs[d]) / ntiles(d).  Work lists are partitioned by
+// pair d (offs[d] <= g < offs[d + 1]) is particle group (g - offs[d]) mod
+// ngroups(d) of tile (g - offs[d]) / ngroups(d).  Work lists are partitioned by
 // XCD: workgroup b serves list b % 8 (the dispatcher hands workgroups to the
 // eight XCDs round robin), so each pair's items stay on one XCD's L2.
 struct BatchArgs {
@@ -465,13 +498,16 @@ __global__ __launch_bounds__(kThreads) void k_batch_score(const BatchArgs b) {
         if (b.kmax[d] < b.k) continue;
         const KArgs &a = b.pairs[d];
         const uint32_t local = g - b.offs[d];
-        const uint32_t nbx = (uint32_t)(a.tiles_x * a.tiles_y) * (uint32_t)((a.tn2 + a.zchunk - 1) / a.zchunk);
+        const uint32_t ng = (a.np + PT - 1) / PT;
+        const uint32_t bx = local / ng, by = local - bx * ng;
         if (MODE == kModeMask) {
-            mask_body<PT>(a, local % nbx, local / nbx);
-        } else if (a.src_ok) {
-            image_body<PT, LAYOUT, true, true>(a, local % nbx, local / nbx);
+            mask_body<PT>(a, bx, by);
+        } else if (a.vmode == 2 && LAYOUT != kLayoutRaw) {
+            image_body<PT, LAYOUT, true, 2>(a, bx, by);
+        } else if (a.vmode != 0) {
+            image_body<PT, LAYOUT, true, 1>(a, bx, by);
         } else {
-            image_body<PT, LAYOUT, true, false>(a, local % nbx, local / nbx);
+            image_body<PT, LAYOUT, true, 0>(a, bx, by);
         }
         __syncthreads();
     }
@@ -482,6 +518,8 @@ KArgs make_args(const ScoreLaunch &L, int pt, int *nz_chunks) {
     a.src = L.src;
     a.src_packed = L.src_packed ? L.src_packed : (const void *)L.src;
     a.src_ok = L.src_ok;
+    a.vmode = L.src_ok == nullptr ? 0 : (L.has_sentinel && L.layout != kLayoutRaw ? 2 : 1);
+    a.sentinel = L.sentinel;
     a.tgt = L.tgt;
     a.tgt_fov = L.tgt_fov;
     a.words = L.words;
@@ -522,17 +560,18 @@ KArgs make_args(const ScoreLaunch &L, int pt, int *nz_chunks) {
 typedef void (*ScoreKernel)(const KArgs);
 
 template <int PT, int LAYOUT>
-ScoreKernel pick_tri(bool sok) {
-    return sok ? k_score_image<PT, LAYOUT, true, true> : k_score_image<PT, LAYOUT, true, false>;
+ScoreKernel pick_tri(int vmode) {
+    if (vmode == 2 && LAYOUT != kLayoutRaw) return k_score_image<PT, LAYOUT, true, 2>;
+    return vmode ? k_score_image<PT, LAYOUT, true, 1> : k_score_image<PT, LAYOUT, true, 0>;
 }
 
 template <int PT>
-ScoreKernel pick_tri_layout(int layout, bool sok) {
+ScoreKernel pick_tri_layout(int layout, int vmode) {
     switch (layout) {
-    case kLayoutPairX: return pick_tri<PT, kLayoutPairX>(sok);
-    case kLayoutQuadXY: return pick_tri<PT, kLayoutQuadXY>(sok);
-    case kLayoutOct: return pick_tri<PT, kLayoutOct>(sok);
-    default: return pick_tri<PT, kLayoutRaw>(sok);
+    case kLayoutPairX: return pick_tri<PT, kLayoutPairX>(vmode);
+    case kLayoutQuadXY: return pick_tri<PT, kLayoutQuadXY>(vmode);
+    case kLayoutOct: return pick_tri<PT, kLayoutOct>(vmode);
+    default: return pick_tri<PT, kLayoutRaw>(vmode);
     }
 }
 
@@ -541,8 +580,8 @@ ScoreKernel pick(const ScoreLaunch &L) {
     if (L.mode == kModeMask) return k_score_mask<PT>;
     const bool sok = L.src_ok != nullptr;
     if (L.mode == kModeImageNearest)
-        return sok ? k_score_image<PT, kLayoutRaw, false, true> : k_score_image<PT, kLayoutRaw, false, false>;
-    return pick_tri_layout<PT>(L.layout, sok);
+        return sok ? k_score_image<PT, kLayoutRaw, false, 1> : k_score_image<PT, kLayoutRaw, false, 0>;
+    return pick_tri_layout<PT>(L.layout, !sok ? 0 : (L.has_sentinel ? 2 : 1));
 }
 
 }  // namespace
@@ -601,7 +640,7 @@ void score_grid(const ScoreLaunch &L, dim3 *grid, dim3 *block) {
     int chunks;
     const int pt = score_pt_supported(L.pt) ? L.pt : 8;
     const KArgs a = make_args(L, pt, &chunks);
-    *grid = dim3((unsigned)(a.tiles_x * a.tiles_y * chunks), (L.np + pt - 1) / pt, 1);
+    *grid = dim3((unsigned)(a.tiles_x * a.tiles_y * chunks) * ((L.np + pt - 1) / pt), 1, 1);
     *block = dim3(kThreads, 1, 1);
 }
 

@@ -375,3 +375,30 @@ def test_autotune_keeps_results(smc, orc):
     t2 = r2.autotune(reps=2)
     assert {k: t2[k] for k in ("layout", "particles_per_group", "tile_depth")} == \
         {k: t[k] for k in ("layout", "particles_per_group", "tile_depth")}
+
+
+def test_fov_sentinel_and_fallback_exact(smc, orc):
+    """Packed layouts mark samples outside the source FOV with a value no
+    in-FOV element takes; when every x-pair value is taken (this source holds
+    all 65536), the x-pair layout falls back to the validity gather.  Both
+    give the oracle's sums."""
+    rows = []
+    for a in range(256):
+        r = np.empty(512, np.uint8)
+        r[0::2] = a
+        r[1::2] = np.arange(256)
+        rows.append(r)
+    src = np.stack([np.stack(rows), np.stack(rows)[::-1]]).astype(np.uint8)  # (2, 256, 512)
+    tgt = np.ascontiguousarray(src[:, ::-1, :])
+    fov = np.ones_like(src)
+    fov[:, 100:140, 200:260] = 0
+    prm = dict(config.default_params("ncc", 24, 2, 5.0, 3.0), min_overlap_frac=0.0)
+    r = _reg(smc, dict(src=src, tgt=tgt), prm, src_fov=fov)
+    x = _random_states(24, 5, 3, 31)
+    x[:, 0] = 0.0
+    x[:, 1] = 0.0  # stay within the two slices
+    x[:, 5] = 0.0
+    want = _oracle_sums(orc, orc.Volume(src, fov=fov), orc.Volume(tgt), x, "trilinear")
+    for layout in ("pairx", "quadxy", "oct", "raw"):
+        r.tune(layout, 4, 32)
+        assert np.array_equal(r.evaluate(x), want), layout
