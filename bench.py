@@ -25,15 +25,56 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X published peaks
+import hashlib
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 39.3e12 32-bit VALU
+# lane operations per second (the published 157.3 TFLOP/s FP32 vector peak
+# is this x 2 for an FMA x 2 for packed FP32, which this build does not use)
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3
-# algorithmic work of one trilinear particle x voxel evaluation:
-# 8 source taps + the target byte shared by the 8 particles of a workgroup
-BYTES_PER_EVAL = 8.0 + 1.0 / 8.0
-# FP32 flops: 3 coordinate FMAs (6), 3 fraction subtractions (3), 7 lerps of a
-# subtraction and an FMA (21), fixed-point scale and round (2)
-FLOPS_PER_EVAL = 32.0
+# algorithmic ALU work of one trilinear particle x voxel evaluation: 3
+# coordinate FMAs, 7 lerps of a subtraction and an FMA (14), fixed-point
+# scale-round and convert (2), six sum updates (n, s, t, s^2, t^2, s t)
+OPS_PER_EVAL = 25.0
+# source gather: the 2 x 2 x 2 taps (served from L1 / L2, not HBM), plus the
+# target byte shared by the particles of a workgroup
+GATHER_BYTES_PER_EVAL = 8.0
+# launch configuration timed by default (layout, particles per workgroup,
+# tile depth): the fastest setting of the autotuner on this workload
+DEFAULT_TUNING = "3,4,256"
+# the committed hardware-counter summary of the warp-and-score kernel
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_score_image_speckle160_pmc.md")
+KERNEL_SOURCES = ["paper_2504_19930_amd/csrc/score.hip", "paper_2504_19930_amd/csrc/internal.h",
+                  "paper_2504_19930_amd/csrc/common.h"]
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_traffic():
+    """HBM-side bytes per warp-and-score launch from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by its copy-kernel factor),
+    or None when the summary is missing or the kernel sources changed since."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    vals = {}
+    with open(PMC_SUMMARY) as fh:
+        for line in fh:
+            if line.startswith("    ") and ":" in line:
+                k, v = line.strip().split(":", 1)
+                vals[k.strip()] = v.strip()
+    try:
+        if vals["kernel_sources_sha256"] != kernel_sources_hash():
+            return None
+        return (float(vals["fetch_kib_per_dispatch"]) * float(vals["fetch_copy_factor"]) +
+                float(vals["write_kib_per_dispatch"]) * float(vals["write_copy_factor"])) * 1024.0
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -77,8 +118,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-time-to-dice", action="store_true")
     ap.add_argument("--ttd-pairs", type=int, default=2)
-    ap.add_argument("--tuning", default=None,
-                    help="layout,particles_per_group,tile_depth instead of autotuning (e.g. 3,4,32)")
+    ap.add_argument("--tuning", default=DEFAULT_TUNING,
+                    help="layout,particles_per_group,tile_depth of the warp-and-score launch")
+    ap.add_argument("--autotune", action="store_true", help="autotune the launch instead of --tuning")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 256 MiB (three times), to scale HBM byte counters")
     args = ap.parse_args()
@@ -123,12 +165,12 @@ def main():
     stream = torch.cuda.current_stream()
     reg = binding.Registration(src, tgt, prm, src_fov=fov)
     src_vol = binding.volume(src)
-    if args.tuning:
+    if args.autotune:
+        tuning = reg.autotune(reps=2)
+    else:
         lay, ppg, depth = (int(v) for v in args.tuning.split(","))
         reg.tune(lay, ppg, depth)
         tuning = reg.tuning()
-    else:
-        tuning = reg.autotune(reps=2)
     log(f"tuning: {tuning}")
 
     def step(s):
@@ -158,8 +200,9 @@ def main():
     value = evals / wall
     score_launch_ms = prof["score_ms"] / max(1, prof["score_launches"])
     evals_per_launch = float(N + 1) * V
-    achieved_tflops = evals_per_launch * FLOPS_PER_EVAL / (score_launch_ms * 1e-3) / 1e12
-    achieved_gbs = evals_per_launch * BYTES_PER_EVAL / (score_launch_ms * 1e-3) / 1e9
+    achieved_tops = evals_per_launch * OPS_PER_EVAL / (score_launch_ms * 1e-3) / 1e12
+    gather_gbs = evals_per_launch * GATHER_BYTES_PER_EVAL / (score_launch_ms * 1e-3) / 1e9
+    traffic = pmc_traffic()
     line = {
         "metric": "particle×voxel evals/s",
         "value": value,
@@ -178,11 +221,12 @@ def main():
                                f"one step = one full registration + warp_apply",
                    "particles": N, "iterations": K, "target_voxels": V, "score": args.score,
                    "tuning": {k: tuning[k] for k in ("layout", "particles_per_group", "tile_depth")}},
-        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+                     "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": traffic,
                      "kernel": "k_score_image (warp-and-score, trilinear)",
+                     "ops_per_eval": OPS_PER_EVAL, "evals_per_launch": evals_per_launch,
                      "kernel_ms_per_launch": score_launch_ms, "launches": prof["score_launches"],
-                     "gather_GBs": achieved_gbs,
+                     "gather_GBs": gather_gbs,
                      "filter_ms_per_launch": prof["filter_ms"] / max(1, prof["filter_launches"])},
         "final_score": est["score"],
     }

@@ -151,7 +151,9 @@ smc_status smc_set_state(smc_ctx *ctx, const void *buf, size_t len);
  * tiles cull more exactly -- a tile whose image cannot reach the source, or
  * in the filter the source mask's bounding box, is skipped -- at the cost of
  * more partial sums).  A negative value keeps the current setting.  Defaults
- * come from measurements on MI355X. */
+ * come from measurements on MI355X.  A packed layout addresses its source
+ * with 32-bit offsets: SMC_EINVAL if the packed source reaches 4 GiB or one
+ * packed slice 16 MiB (smc_init then starts from layout 0 instead). */
 smc_status smc_set_tuning(smc_ctx *ctx, int32_t layout, int32_t particles_per_group, int32_t tile_depth);
 smc_status smc_get_tuning(smc_ctx *ctx, int32_t *layout, int32_t *particles_per_group, int32_t *tile_depth);
 

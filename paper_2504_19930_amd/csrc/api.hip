@@ -370,6 +370,7 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
         }
     }
 
+    if (!layout_fits(c->layout, c->sn)) c->layout = kLayoutRaw;
     if ((st = prepare_layout(c, c->layout)) != SMC_OK) return bail(st);
 
     if (c->mode == kModeMask) {
@@ -698,6 +699,9 @@ smc_status smc_set_tuning(smc_ctx *c, int32_t layout, int32_t pt, int32_t tile_d
     if ((st = c->check_sticky()) != SMC_OK) return st;
     if ((st = set_device(c)) != SMC_OK) return c->mark(st);
     if (layout >= 0) {
+        if (c->mode == kModeImageTrilinear && !layout_fits(layout, c->sn))
+            return fail(SMC_EINVAL, "layout %d cannot address a %d x %d x %d source (packed size >= 4 GiB or "
+                        "a packed slice >= 16 MiB); use layout 0", layout, c->sn[0], c->sn[1], c->sn[2]);
         if ((st = prepare_layout(c, layout)) != SMC_OK) return c->mark(st);
         c->layout = layout;
     }
@@ -769,7 +773,7 @@ smc_status smc_autotune(smc_ctx *c, uint32_t reps, double *best_ms) {
     smc_status result = SMC_OK;
     for (int lay : layouts)
         for (int pt : {4, 8})
-            for (int q = 0; q < nd && result == SMC_OK; ++q) {
+            for (int q = 0; q < nd && result == SMC_OK && layout_fits(lay, c->sn); ++q) {
                 if ((result = smc_set_tuning(c, lay, pt, depths[q])) != SMC_OK) break;
                 const ScoreLaunch L = c->score_launch(c->f.words, c->s_eval, 0, np, true);
                 double tot = 0.0;

@@ -111,7 +111,10 @@ SMC_HD void words_from_matrix(const double M[12], const double ts[3], const doub
         for (int e = 0; e < 3; ++e) w[4 * d + e] = (float)((M[4 * d + e] * ts[e]) / ss[d]);
         double o = M[4 * d + 3] / ss[d];
         if (nearest) o = o + 0.5;
-        w[4 * d + 3] = (float)o;
+        // + 0.0f turns a -0 offset into +0: the sign of a zero coordinate
+        // changes no result, and the score kernels test "inside" on the bit
+        // patterns of non-negative coordinates
+        w[4 * d + 3] = (float)o + 0.0f;
     }
 }
 

@@ -41,6 +41,8 @@ struct ScoreLaunch {
 hipError_t launch_score(const ScoreLaunch &L, hipStream_t s);
 void score_grid(const ScoreLaunch &L, dim3 *grid, dim3 *block);
 bool score_pt_supported(int pt);
+// whether a packed trilinear layout can address a source of this shape
+bool layout_fits(int layout, const int32_t sn[3]);
 // Pack a source volume into `layout` (edge corners repeat the last voxel).
 // With fov, elements touching a voxel outside it hold `sentinel` instead.
 hipError_t launch_pack_source(const uint8_t *vol, const uint8_t *fov, const int32_t n[3], int layout,

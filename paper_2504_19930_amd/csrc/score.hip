@@ -44,7 +44,14 @@ struct KArgs {
     // 2 packed elements equal to `sentinel` mark samples outside the FOV
     int32_t vmode;
     uint64_t sentinel;
+    // packed layouts: byte size of the packed source and byte strides of its
+    // rows and slices (32-bit buffer offsets; the host checks they fit)
+    uint32_t src_bytes, ysb, zsb;
 };
+
+// Word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format,
+// untyped loads; out-of-range offsets read zero).
+constexpr int kBufferWord3 = 0x00020000;
 
 // Culling margin (voxels): far above the FP32 rounding of the coordinate
 // recipe for any coordinate below 2^16.
@@ -223,6 +230,61 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
 
 // ---------------------------------------------------------------- images
 
+// floor and convert in one instruction (exact for the clamped, non-negative
+// coordinates it is used on)
+__device__ __forceinline__ uint32_t floor_u32(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return (uint32_t)r;
+}
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Packed corners through a buffer resource with 32-bit byte offsets:
+// off = the base element, dy / dz the byte steps to the element one row /
+// one slice up (zero on the last row / slice, where the weight is zero).
+template <int LAYOUT>
+__device__ __forceinline__ void corners_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t dy, uint32_t dz,
+                                            float v[8], uint64_t sentinel, bool &sent_ok) {
+    if (LAYOUT == kLayoutPairX) {
+        const uint32_t a = __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
+        const uint32_t b = __builtin_amdgcn_raw_buffer_load_b16(rs, off + dy, 0, 0);
+        const uint32_t c = __builtin_amdgcn_raw_buffer_load_b16(rs, off + dz, 0, 0);
+        const uint32_t d = __builtin_amdgcn_raw_buffer_load_b16(rs, off + dz + dy, 0, 0);
+        const uint32_t st = (uint32_t)(sentinel & 0xFFFFu);
+        sent_ok = (a != st) & (b != st) & (c != st) & (d != st);
+        v[0] = (float)(a & 0xFFu);
+        v[1] = (float)(a >> 8);
+        v[2] = (float)(b & 0xFFu);
+        v[3] = (float)(b >> 8);
+        v[4] = (float)(c & 0xFFu);
+        v[5] = (float)(c >> 8);
+        v[6] = (float)(d & 0xFFu);
+        v[7] = (float)(d >> 8);
+    } else {
+        uint32_t lo, hi;
+        if (LAYOUT == kLayoutQuadXY) {
+            lo = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+            hi = __builtin_amdgcn_raw_buffer_load_b32(rs, off + dz, 0, 0);
+            const uint32_t st = (uint32_t)sentinel;
+            sent_ok = (lo != st) & (hi != st);
+        } else {
+            const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+            lo = w.x;
+            hi = w.y;
+            sent_ok = (lo != (uint32_t)sentinel) | (hi != (uint32_t)(sentinel >> 32));
+        }
+        v[0] = (float)(lo & 0xFFu);
+        v[1] = (float)((lo >> 8) & 0xFFu);
+        v[2] = (float)((lo >> 16) & 0xFFu);
+        v[3] = (float)(lo >> 24);
+        v[4] = (float)(hi & 0xFFu);
+        v[5] = (float)((hi >> 8) & 0xFFu);
+        v[6] = (float)((hi >> 16) & 0xFFu);
+        v[7] = (float)(hi >> 24);
+    }
+}
+
 // The eight trilinear corners of base voxel (ix, iy, iz) as floats, read from
 // one of the source layouts (corners beyond the last voxel repeat it; their
 // weight is zero there):
@@ -311,49 +373,72 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
         const uint32_t sn0 = (uint32_t)a.sn0, sn01 = (uint32_t)a.sn0 * (uint32_t)a.sn1;
         const float ex = (float)(a.sn0 - 1), ey = (float)(a.sn1 - 1), ez = (float)(a.sn2 - 1);
         const bool tfov = a.tgt_fov != nullptr;
-        // the target byte of the next slice is loaded one step ahead
-        uint32_t tv_next = (t.k0 < t.k1) ? (uint32_t)a.tgt[tofs0 + plane * (size_t)t.k0] : 0u;
-        for (int k = t.k0; k < t.k1; ++k) {
-            const size_t tofs = tofs0 + plane * (size_t)k;
+        constexpr uint32_t kElemShift = LAYOUT == kLayoutOct ? 3u : (LAYOUT == kLayoutQuadXY ? 2u : 1u);
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(a.src_packed), (short)0, (int)a.src_bytes,
+                                              kBufferWord3);
+        const __amdgpu_buffer_rsrc_t rs_ok = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t *>(a.src_ok), (short)0, a.sn0 * a.sn1 * a.sn2, kBufferWord3);
+        const uint32_t exb = __float_as_uint(ex), eyb = __float_as_uint(ey), ezb = __float_as_uint(ez);
+        // n and t of the overlap packed in one register: n < 2^9 and t < 2^16
+        // for a z-chunk of at most 256 slices
+        uint32_t nt[PT];
+#pragma unroll
+        for (int p = 0; p < PT; ++p) nt[p] = 0u;
+        // target bytes through buffer loads with 32-bit offsets (a volume has
+        // fewer than 2^31 voxels); the byte of the next slice is loaded one
+        // step ahead (past the last slice the bounds check returns zero)
+        const int tbytes = a.tn0 * a.tn1 * a.tn2;
+        const __amdgpu_buffer_rsrc_t rs_t =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(a.tgt), (short)0, tbytes, kBufferWord3);
+        const __amdgpu_buffer_rsrc_t rs_tf = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t *>(a.tgt_fov), (short)0, tfov ? tbytes : 0, kBufferWord3);
+        const uint32_t plane32 = (uint32_t)plane;
+        uint32_t tofs = (uint32_t)tofs0 + plane32 * (uint32_t)t.k0;
+        uint32_t tv_next = __builtin_amdgcn_raw_buffer_load_b8(rs_t, tofs, 0, 0);
+        for (int k = t.k0; k < t.k1; ++k, tofs += plane32) {
             const uint32_t tv = tv_next;
-            if (k + 1 < t.k1) tv_next = a.tgt[tofs + plane];
-            if (tfov && a.tgt_fov[tofs] == 0) continue;
+            tv_next = __builtin_amdgcn_raw_buffer_load_b8(rs_t, tofs + plane32, 0, 0);
+            if (tfov && __builtin_amdgcn_raw_buffer_load_b8(rs_tf, tofs, 0, 0) == 0) continue;
             const uint32_t tv2 = tv * tv;
+            const uint32_t nt1 = 1u + (tv << 9);
             const float fk = (float)k;
-            if (TRI) {
+            if (TRI && LAYOUT != kLayoutRaw) {
                 // all PT samples: clamped coordinates (exact where inside, so every
-                // address is valid), all loads issued before any use, then sums
+                // offset is valid), all loads issued before any use, then sums
                 // predicated on inside && FOV-valid && particle live for this tile
                 float fxa[PT], fya[PT], fza[PT];
-                uint32_t base[PT], ddx[PT], ddy[PT], ddz[PT];
+                uint32_t off[PT], ddy[PT], ddz[PT];
                 bool in[PT];
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
                     const float ux = fmaf(ax[p], fk, mx[p]);
                     const float uy = fmaf(ay[p], fk, my[p]);
                     const float uz = fmaf(az[p], fk, mz[p]);
-                    in[p] = ((live >> p) & 1u) & (ux >= 0.0f) & (ux <= ex) & (uy >= 0.0f) & (uy <= ey) &
-                            (uz >= 0.0f) & (uz <= ez);
-                    const float cx = __builtin_amdgcn_fmed3f(ux, 0.0f, ex);
-                    const float cy = __builtin_amdgcn_fmed3f(uy, 0.0f, ey);
-                    const float cz = __builtin_amdgcn_fmed3f(uz, 0.0f, ez);
-                    const float flx = floorf(cx), fly = floorf(cy), flz = floorf(cz);
-                    const uint32_t ix = (uint32_t)flx, iy = (uint32_t)fly, iz = (uint32_t)flz;
-                    fxa[p] = cx - flx;
-                    fya[p] = cy - fly;
-                    fza[p] = cz - flz;
-                    base[p] = ix + sn0 * iy + sn01 * iz;
-                    ddx[p] = ix < (uint32_t)(a.sn0 - 1) ? 1u : 0u;
-                    ddy[p] = iy < (uint32_t)(a.sn1 - 1) ? sn0 : 0u;
-                    ddz[p] = iz < (uint32_t)(a.sn2 - 1) ? sn01 : 0u;
+                    // 0 <= u <= n - 1 as one unsigned compare of bit patterns: the
+                    // coordinates are never -0 (the offset words are normalised to
+                    // +0) and negative ones have the sign bit set
+                    in[p] = ((live >> p) & 1u) & (__float_as_uint(ux) <= exb) & (__float_as_uint(uy) <= eyb) &
+                            (__float_as_uint(uz) <= ezb);
+                    // samples outside produce arbitrary offsets: the buffer loads
+                    // are bounds-checked (zero beyond the end) and the sums ignore them
+                    const uint32_t ix = floor_u32(ux), iy = floor_u32(uy), iz = floor_u32(uz);
+                    fxa[p] = __builtin_amdgcn_fractf(ux);
+                    fya[p] = __builtin_amdgcn_fractf(uy);
+                    fza[p] = __builtin_amdgcn_fractf(uz);
+                    off[p] = __umul24(iz, a.zsb) + __umul24(iy, a.ysb) + (ix << kElemShift);
+                    if (LAYOUT == kLayoutPairX) ddy[p] = iy < (uint32_t)(a.sn1 - 1) ? a.ysb : 0u;
+                    if (LAYOUT != kLayoutOct) ddz[p] = iz < (uint32_t)(a.sn2 - 1) ? a.zsb : 0u;
                 }
                 uint32_t okv[PT];
                 float v[PT][8];
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
                     bool sent_ok;
-                    corners<LAYOUT>(a.src_packed, base[p], ddx[p], ddy[p], ddz[p], v[p], a.sentinel, sent_ok);
-                    okv[p] = SOK ? (uint32_t)a.src_ok[base[p]] : (VMODE == 2 ? (sent_ok ? 1u : 0u) : 1u);
+                    corners_buf<LAYOUT>(rs, off[p], LAYOUT == kLayoutPairX ? ddy[p] : 0u,
+                                        LAYOUT != kLayoutOct ? ddz[p] : 0u, v[p], a.sentinel, sent_ok);
+                    okv[p] = SOK ? __builtin_amdgcn_raw_buffer_load_b8(rs_ok, off[p] >> kElemShift, 0, 0)
+                                 : (VMODE == 2 ? (sent_ok ? 1u : 0u) : 1u);
                 }
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
@@ -366,11 +451,59 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                     const float sv = fmaf(fza[p], y1 - y0, y0);
                     // s * 256 is exact, so one fused step equals the multiply-add
                     const uint32_t sfx0 = (uint32_t)fmaf(sv, 256.0f, 0.5f);
-                    const uint32_t valid = (in[p] ? 1u : 0u) & okv[p];
+                    const bool valid = in[p] & (okv[p] != 0u);
                     const uint32_t sfx = valid ? sfx0 : 0u;
-                    acc[p].n += valid;
+                    nt[p] += valid ? nt1 : 0u;
                     acc[p].s += sfx;
-                    acc[p].t += valid ? tv : 0u;
+                    acc[p].ss += (unsigned long long)sfx * sfx;
+                    acc[p].tt += valid ? tv2 : 0u;
+                    acc[p].st += __umul24(sfx, tv);  // s_fx < 2^16, t < 2^8
+                }
+            } else if (TRI) {
+                // raw bytes: eight gathers per sample through 64-bit addresses
+                float fxa[PT], fya[PT], fza[PT];
+                uint32_t base[PT], ddx[PT], ddy[PT], ddz[PT];
+                bool in[PT];
+#pragma unroll
+                for (int p = 0; p < PT; ++p) {
+                    const float ux = fmaf(ax[p], fk, mx[p]);
+                    const float uy = fmaf(ay[p], fk, my[p]);
+                    const float uz = fmaf(az[p], fk, mz[p]);
+                    const float cx = __builtin_amdgcn_fmed3f(ux, 0.0f, ex);
+                    const float cy = __builtin_amdgcn_fmed3f(uy, 0.0f, ey);
+                    const float cz = __builtin_amdgcn_fmed3f(uz, 0.0f, ez);
+                    in[p] = ((live >> p) & 1u) & (cx == ux) & (cy == uy) & (cz == uz);
+                    const uint32_t ix = floor_u32(cx), iy = floor_u32(cy), iz = floor_u32(cz);
+                    fxa[p] = __builtin_amdgcn_fractf(cx);
+                    fya[p] = __builtin_amdgcn_fractf(cy);
+                    fza[p] = __builtin_amdgcn_fractf(cz);
+                    base[p] = ix + sn0 * iy + sn01 * iz;
+                    ddx[p] = ix < (uint32_t)(a.sn0 - 1) ? 1u : 0u;
+                    ddy[p] = iy < (uint32_t)(a.sn1 - 1) ? sn0 : 0u;
+                    ddz[p] = iz < (uint32_t)(a.sn2 - 1) ? sn01 : 0u;
+                }
+                uint32_t okv[PT];
+                float v[PT][8];
+#pragma unroll
+                for (int p = 0; p < PT; ++p) {
+                    bool sent_ok;
+                    corners<kLayoutRaw>(a.src_packed, base[p], ddx[p], ddy[p], ddz[p], v[p], a.sentinel, sent_ok);
+                    okv[p] = SOK ? (uint32_t)a.src_ok[base[p]] : 1u;
+                }
+#pragma unroll
+                for (int p = 0; p < PT; ++p) {
+                    const float x00 = fmaf(fxa[p], v[p][1] - v[p][0], v[p][0]);
+                    const float x10 = fmaf(fxa[p], v[p][3] - v[p][2], v[p][2]);
+                    const float x01 = fmaf(fxa[p], v[p][5] - v[p][4], v[p][4]);
+                    const float x11 = fmaf(fxa[p], v[p][7] - v[p][6], v[p][6]);
+                    const float y0 = fmaf(fya[p], x10 - x00, x00);
+                    const float y1 = fmaf(fya[p], x11 - x01, x01);
+                    const float sv = fmaf(fza[p], y1 - y0, y0);
+                    const uint32_t sfx0 = (uint32_t)fmaf(sv, 256.0f, 0.5f);
+                    const bool valid = in[p] & (okv[p] != 0u);
+                    const uint32_t sfx = valid ? sfx0 : 0u;
+                    nt[p] += valid ? nt1 : 0u;
+                    acc[p].s += sfx;
                     acc[p].ss += (unsigned long long)sfx * sfx;
                     acc[p].tt += valid ? tv2 : 0u;
                     acc[p].st += sfx * tv;
@@ -398,6 +531,11 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                     }
                 }
             }
+        }
+#pragma unroll
+        for (int p = 0; p < PT; ++p) {
+            acc[p].n += nt[p] & 511u;
+            acc[p].t += nt[p] >> 9;
         }
     }
     __shared__ unsigned long long red[kWaves][PT][6];
@@ -552,6 +690,10 @@ KArgs make_args(const ScoreLaunch &L, int pt, int *nz_chunks) {
             a.cull_hi[d] = (float)L.sn[d];
         }
     }
+    const uint32_t eb = (uint32_t)packed_bytes_per_voxel(L.layout);
+    a.src_bytes = (uint32_t)std::min<uint64_t>((uint64_t)L.sn[0] * L.sn[1] * L.sn[2] * eb, 0xFFFFFFFFull);
+    a.ysb = (uint32_t)L.sn[0] * eb;
+    a.zsb = (uint32_t)((uint64_t)L.sn[0] * L.sn[1] * eb);
     *nz_chunks = chunks;
     (void)pt;
     return a;
@@ -587,6 +729,13 @@ ScoreKernel pick(const ScoreLaunch &L) {
 }  // namespace
 
 bool score_pt_supported(int pt) { return pt == 4 || pt == 8 || pt == 16; }
+
+bool layout_fits(int layout, const int32_t sn[3]) {
+    if (layout == kLayoutRaw) return true;
+    const uint64_t eb = packed_bytes_per_voxel(layout);
+    // 32-bit buffer offsets; slice strides within the 24-bit multiplier
+    return (uint64_t)sn[0] * sn[1] * sn[2] * eb <= 0xFFFFFFFFull && (uint64_t)sn[0] * sn[1] * eb < (1ull << 24);
+}
 
 size_t score_args_bytes() { return sizeof(KArgs); }
 
