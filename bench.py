@@ -27,10 +27,10 @@ if ROOT not in sys.path:
 
 import hashlib
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 39.3e12 32-bit VALU
-# lane operations per second (the published 157.3 TFLOP/s FP32 vector peak
-# is this x 2 for an FMA x 2 for packed FP32, which this build does not use)
-PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# MI355X VALU issue: the published FP32 vector peak, 157.3 TFLOP/s, is 256
+# CUs x 128 lane-FMAs per clock x 2.4 GHz x 2 flops; one 32-bit VALU lane
+# operation per lane slot gives 78.6e12 operations per second
+PEAK_VALU_TOPS = 256 * 128 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 # algorithmic ALU work of one trilinear particle x voxel evaluation: 3
 # coordinate FMAs, 7 lerps of a subtraction and an FMA (14), fixed-point
