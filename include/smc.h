@@ -144,8 +144,10 @@ smc_status smc_set_state(smc_ctx *ctx, const void *buf, size_t len);
 /* Launch tuning of the warp-and-score kernel; results do not depend on it.
  * layout: trilinear source layout, 0 raw bytes (eight gathers per sample),
  * 1 x-pairs (uint16, four), 2 2x2 quads (uint32, two), 3 2x2x2 octets
- * (uint64, one); packed layouts cost 2, 4 or 8 bytes per source voxel of
- * device memory, prepared on the stream.  particles_per_group: particles
+ * (uint64, one), 4 the same octets stored in 4 x 4 voxel tiles of a slice
+ * (one 128-byte cache line per tile, so a rotated footprint touches fewer
+ * lines); packed layouts cost 2, 4 or 8 bytes per source voxel of device
+ * memory, prepared on the stream.  particles_per_group: particles
  * sharing one pass over a target column, 4, 8 or 16.  tile_depth: target
  * slices per tile, 1 .. 256 (a tile is 32 x 8 x tile_depth voxels; shallower
  * tiles cull more exactly -- a tile whose image cannot reach the source, or

@@ -118,9 +118,9 @@ struct smc_ctx {
     uint8_t *src_prep = nullptr, *tgt_prep = nullptr, *src_ok = nullptr;
     int layout = kDefaultLayout, pt = kDefaultPT, zchunk = kDefaultZChunk;
     int32_t box_lo[3] = {1, 1, 1}, box_hi[3] = {-1, -1, -1};  // source mask bounding box (empty)
-    void *packed[4] = {nullptr, nullptr, nullptr, nullptr};
-    uint64_t sentinel[4] = {0, 0, 0, 0};  // per packed layout: value marking elements outside the source FOV
-    bool has_sentinel[4] = {false, false, false, false};
+    void *packed[kLayouts] = {};
+    uint64_t sentinel[kLayouts] = {};  // per packed layout: value marking elements outside the source FOV
+    bool has_sentinel[kLayouts] = {};
     FilterState f{};
     uint32_t k_done = 0;
     smc_status sticky = SMC_OK;
@@ -244,9 +244,8 @@ uint64_t splitmix64(uint64_t x) {
 // validity gather); if none is free, pack plainly and keep the gather.
 smc_status prepare_layout(smc_ctx *c, int layout) {
     if (c->mode != kModeImageTrilinear || layout == kLayoutRaw || c->packed[layout]) return SMC_OK;
-    const int64_t vs = (int64_t)c->sn[0] * c->sn[1] * c->sn[2];
     smc_status st;
-    if ((st = c->alloc((uint8_t **)&c->packed[layout], vs * packed_bytes_per_voxel(layout))) != SMC_OK) return st;
+    if ((st = c->alloc((uint8_t **)&c->packed[layout], packed_bytes(layout, c->sn))) != SMC_OK) return st;
     uint64_t sent = 0;
     bool ok = false;
     if (c->src_fov) {
@@ -693,7 +692,7 @@ smc_status smc_set_state(smc_ctx *c, const void *buf, size_t len) {
 smc_status smc_set_tuning(smc_ctx *c, int32_t layout, int32_t pt, int32_t tile_depth) {
     if (!c) return fail(SMC_EINVAL, "ctx is NULL");
     if (tile_depth == 0 || tile_depth > 256) return fail(SMC_EINVAL, "tile_depth must be in 1..256");
-    if (layout > kLayoutOct) return fail(SMC_EINVAL, "unknown layout %d", layout);
+    if (layout >= kLayouts) return fail(SMC_EINVAL, "unknown layout %d", layout);
     if (pt >= 0 && !score_pt_supported(pt)) return fail(SMC_EINVAL, "particles_per_group must be 4, 8 or 16");
     smc_status st;
     if ((st = c->check_sticky()) != SMC_OK) return st;
@@ -762,7 +761,7 @@ smc_status smc_autotune(smc_ctx *c, uint32_t reps, double *best_ms) {
     const uint32_t np = c->f.n + 1;
     if ((st = ensure_eval(c, np)) != SMC_OK) return c->mark(st);
     std::vector<int> layouts = {kLayoutRaw};
-    if (c->mode == kModeImageTrilinear) layouts = {kLayoutRaw, kLayoutPairX, kLayoutQuadXY, kLayoutOct};
+    if (c->mode == kModeImageTrilinear) layouts = {kLayoutRaw, kLayoutPairX, kLayoutQuadXY, kLayoutOct, kLayoutOctTile};
     const int depths_img[] = {32, 256}, depths_mask[] = {16, 32, 256};
     const int *depths = c->mode == kModeMask ? depths_mask : depths_img;
     const int nd = c->mode == kModeMask ? 3 : 2;

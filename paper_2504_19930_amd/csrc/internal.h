@@ -14,7 +14,8 @@ enum ScoreMode : int { kModeMask = 0, kModeImageTrilinear = 1, kModeImageNearest
 
 // Source layouts for trilinear sampling (see score.hip): bytes per voxel
 // 1, 2, 4, 8; eight, four, two or one gathers per sample.
-enum SourceLayout : int { kLayoutRaw = 0, kLayoutPairX = 1, kLayoutQuadXY = 2, kLayoutOct = 3 };
+enum SourceLayout : int { kLayoutRaw = 0, kLayoutPairX = 1, kLayoutQuadXY = 2, kLayoutOct = 3, kLayoutOctTile = 4 };
+constexpr int kLayouts = 5;
 
 struct ScoreLaunch {
     int mode;
@@ -53,6 +54,8 @@ hipError_t launch_pack_source(const uint8_t *vol, const uint8_t *fov, const int3
 hipError_t launch_count_elements(const uint8_t *vol, const uint8_t *fov, const int32_t n[3], int layout,
                                  const uint64_t *cand, int n_cand, unsigned long long *counts, hipStream_t s);
 size_t packed_bytes_per_voxel(int layout);
+// bytes of a packed source of shape n (the tiled layout pads x and y to 4)
+uint64_t packed_bytes(int layout, const int32_t n[3]);
 
 // Batched warp-and-score: one persistent launch over the work items of many
 // pairs of one class (masks, or trilinear images in one layout).

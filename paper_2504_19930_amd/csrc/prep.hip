@@ -117,9 +117,21 @@ __global__ void k_pack_source(const uint8_t *vol, const uint8_t *fov, int32_t nx
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         const Elem e = element(vol, fov, nx, ny, nz, layout, q);
         const uint64_t v = e.valid ? e.value : sentinel;
-        if (layout == kLayoutPairX) ((uint16_t *)out)[q] = (uint16_t)v;
-        else if (layout == kLayoutQuadXY) ((uint32_t *)out)[q] = (uint32_t)v;
-        else ((uint2 *)out)[q] = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+        if (layout == kLayoutPairX) {
+            ((uint16_t *)out)[q] = (uint16_t)v;
+        } else if (layout == kLayoutQuadXY) {
+            ((uint32_t *)out)[q] = (uint32_t)v;
+        } else {
+            int64_t o = q;
+            if (layout == kLayoutOctTile) {
+                // 4 x 4 tiles of one slice, 16 octets (128 bytes) each, x fastest
+                // inside a tile, tiles x fastest, then y, then slices
+                const int64_t i = q % nx, j = (q / nx) % ny, k = q / ((int64_t)nx * ny);
+                const int64_t tx = (nx + 3) / 4, ty = (ny + 3) / 4;
+                o = ((k * ty + j / 4) * tx + i / 4) * 16 + (j % 4) * 4 + (i % 4);
+            }
+            ((uint2 *)out)[o] = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+        }
     }
 }
 
@@ -185,9 +197,15 @@ size_t packed_bytes_per_voxel(int layout) {
     switch (layout) {
     case kLayoutPairX: return 2;
     case kLayoutQuadXY: return 4;
-    case kLayoutOct: return 8;
+    case kLayoutOct: case kLayoutOctTile: return 8;
     default: return 1;
     }
+}
+
+uint64_t packed_bytes(int layout, const int32_t n[3]) {
+    if (layout == kLayoutOctTile)
+        return (uint64_t)((n[0] + 3) / 4) * (uint64_t)((n[1] + 3) / 4) * 128ull * (uint64_t)n[2];
+    return (uint64_t)n[0] * n[1] * n[2] * packed_bytes_per_voxel(layout);
 }
 
 hipError_t launch_pack_source(const uint8_t *vol, const uint8_t *fov, const int32_t n[3], int layout,

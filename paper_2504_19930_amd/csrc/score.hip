@@ -26,6 +26,8 @@ namespace {
 constexpr int kTX = 32;
 constexpr int kTY = 8;
 constexpr int kThreads = kTX * kTY;
+constexpr int kWX = 16;  // wave patch width (x); 64 / kWX rows
+static_assert(kTX % kWX == 0 && 64 % kWX == 0 && kTY % (64 / kWX) == 0, "waves must tile the 32 x 8 column");
 constexpr int kWaves = kThreads / 64;
 constexpr int kZChunkMax = 256;  // keeps every per-thread 32-bit sum below 2^32
 
@@ -84,8 +86,11 @@ __device__ __forceinline__ Tile tile_of(const KArgs &a, uint32_t bx, uint32_t by
     b -= zc * tiles;
     const int ty = b / a.tiles_x;
     const int tx = b - ty * a.tiles_x;
-    t.i = tx * kTX + (int)(threadIdx.x % kTX);
-    t.j = ty * kTY + (int)(threadIdx.x / kTX);
+    // each wave covers a kWX x (64 / kWX) patch of the tile: a squarer patch
+    // maps to fewer source cache lines under rotation
+    const int lane = (int)(threadIdx.x % 64), wave = (int)(threadIdx.x / 64);
+    t.i = tx * kTX + (wave % (kTX / kWX)) * kWX + lane % kWX;
+    t.j = ty * kTY + (wave / (kTX / kWX)) * (64 / kWX) + lane / kWX;
     t.ok = t.i < a.tn0 && t.j < a.tn1;
     t.k0 = zc * a.zchunk;
     t.k1 = min(t.k0 + a.zchunk, a.tn2);
@@ -373,7 +378,8 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
         const uint32_t sn0 = (uint32_t)a.sn0, sn01 = (uint32_t)a.sn0 * (uint32_t)a.sn1;
         const float ex = (float)(a.sn0 - 1), ey = (float)(a.sn1 - 1), ez = (float)(a.sn2 - 1);
         const bool tfov = a.tgt_fov != nullptr;
-        constexpr uint32_t kElemShift = LAYOUT == kLayoutOct ? 3u : (LAYOUT == kLayoutQuadXY ? 2u : 1u);
+        constexpr uint32_t kElemShift =
+            LAYOUT == kLayoutOct || LAYOUT == kLayoutOctTile ? 3u : (LAYOUT == kLayoutQuadXY ? 2u : 1u);
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(a.src_packed), (short)0, (int)a.src_bytes,
                                               kBufferWord3);
@@ -408,7 +414,7 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                 // offset is valid), all loads issued before any use, then sums
                 // predicated on inside && FOV-valid && particle live for this tile
                 float fxa[PT], fya[PT], fza[PT];
-                uint32_t off[PT], ddy[PT], ddz[PT];
+                uint32_t off[PT], ddy[PT], ddz[PT], vidx[PT];
                 bool in[PT];
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
@@ -426,9 +432,21 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                     fxa[p] = __builtin_amdgcn_fractf(ux);
                     fya[p] = __builtin_amdgcn_fractf(uy);
                     fza[p] = __builtin_amdgcn_fractf(uz);
-                    off[p] = __umul24(iz, a.zsb) + __umul24(iy, a.ysb) + (ix << kElemShift);
+                    if (LAYOUT == kLayoutOctTile) {
+                        // (ix / 4) * 128 + (ix % 4) * 8 + (iy / 4) * 4 ysb + (iy % 4) * 32
+                        // + iz * zsb, with ysb = 32 ceil(nx / 4) (signed 24-bit
+                        // multiplies; arbitrary but in-buffer-checked for outside samples)
+                        uint32_t o = __mul24((int)(ix & 3u), -24) + (ix << 5);
+                        o += __mul24((int)(iy & 3u), 32 - (int)a.ysb);
+                        off[p] = o + __umul24(iy, a.ysb) + __umul24(iz, a.zsb);
+                        if (SOK) vidx[p] = ix + sn0 * iy + sn01 * iz;
+                    } else {
+                        off[p] = __umul24(iz, a.zsb) + __umul24(iy, a.ysb) + (ix << kElemShift);
+                        if (SOK) vidx[p] = off[p] >> kElemShift;
+                    }
                     if (LAYOUT == kLayoutPairX) ddy[p] = iy < (uint32_t)(a.sn1 - 1) ? a.ysb : 0u;
-                    if (LAYOUT != kLayoutOct) ddz[p] = iz < (uint32_t)(a.sn2 - 1) ? a.zsb : 0u;
+                    if (LAYOUT == kLayoutPairX || LAYOUT == kLayoutQuadXY)
+                        ddz[p] = iz < (uint32_t)(a.sn2 - 1) ? a.zsb : 0u;
                 }
                 uint32_t okv[PT];
                 float v[PT][8];
@@ -436,8 +454,9 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                 for (int p = 0; p < PT; ++p) {
                     bool sent_ok;
                     corners_buf<LAYOUT>(rs, off[p], LAYOUT == kLayoutPairX ? ddy[p] : 0u,
-                                        LAYOUT != kLayoutOct ? ddz[p] : 0u, v[p], a.sentinel, sent_ok);
-                    okv[p] = SOK ? __builtin_amdgcn_raw_buffer_load_b8(rs_ok, off[p] >> kElemShift, 0, 0)
+                                        LAYOUT == kLayoutPairX || LAYOUT == kLayoutQuadXY ? ddz[p] : 0u, v[p],
+                                        a.sentinel, sent_ok);
+                    okv[p] = SOK ? __builtin_amdgcn_raw_buffer_load_b8(rs_ok, vidx[p], 0, 0)
                                  : (VMODE == 2 ? (sent_ok ? 1u : 0u) : 1u);
                 }
 #pragma unroll
@@ -691,9 +710,14 @@ KArgs make_args(const ScoreLaunch &L, int pt, int *nz_chunks) {
         }
     }
     const uint32_t eb = (uint32_t)packed_bytes_per_voxel(L.layout);
-    a.src_bytes = (uint32_t)std::min<uint64_t>((uint64_t)L.sn[0] * L.sn[1] * L.sn[2] * eb, 0xFFFFFFFFull);
-    a.ysb = (uint32_t)L.sn[0] * eb;
-    a.zsb = (uint32_t)((uint64_t)L.sn[0] * L.sn[1] * eb);
+    a.src_bytes = (uint32_t)std::min<uint64_t>(packed_bytes(L.layout, L.sn), 0xFFFFFFFFull);
+    if (L.layout == kLayoutOctTile) {
+        a.ysb = 32u * (uint32_t)((L.sn[0] + 3) / 4);  // a quarter of a row of tiles
+        a.zsb = (uint32_t)(128ull * (uint64_t)((L.sn[0] + 3) / 4) * (uint64_t)((L.sn[1] + 3) / 4));
+    } else {
+        a.ysb = (uint32_t)L.sn[0] * eb;
+        a.zsb = (uint32_t)((uint64_t)L.sn[0] * L.sn[1] * eb);
+    }
     *nz_chunks = chunks;
     (void)pt;
     return a;
@@ -713,6 +737,7 @@ ScoreKernel pick_tri_layout(int layout, int vmode) {
     case kLayoutPairX: return pick_tri<PT, kLayoutPairX>(vmode);
     case kLayoutQuadXY: return pick_tri<PT, kLayoutQuadXY>(vmode);
     case kLayoutOct: return pick_tri<PT, kLayoutOct>(vmode);
+    case kLayoutOctTile: return pick_tri<PT, kLayoutOctTile>(vmode);
     default: return pick_tri<PT, kLayoutRaw>(vmode);
     }
 }
@@ -732,9 +757,9 @@ bool score_pt_supported(int pt) { return pt == 4 || pt == 8 || pt == 16; }
 
 bool layout_fits(int layout, const int32_t sn[3]) {
     if (layout == kLayoutRaw) return true;
-    const uint64_t eb = packed_bytes_per_voxel(layout);
     // 32-bit buffer offsets; slice strides within the 24-bit multiplier
-    return (uint64_t)sn[0] * sn[1] * sn[2] * eb <= 0xFFFFFFFFull && (uint64_t)sn[0] * sn[1] * eb < (1ull << 24);
+    const int32_t one[3] = {sn[0], sn[1], 1};
+    return packed_bytes(layout, sn) <= 0xFFFFFFFFull && packed_bytes(layout, one) < (1ull << 24);
 }
 
 size_t score_args_bytes() { return sizeof(KArgs); }
@@ -760,6 +785,7 @@ ScoreKernel pick_batch(int mode, int layout) {
     else if (layout == kLayoutPairX) k = k_batch_score<PT, kModeImageTrilinear, kLayoutPairX>;
     else if (layout == kLayoutQuadXY) k = k_batch_score<PT, kModeImageTrilinear, kLayoutQuadXY>;
     else if (layout == kLayoutOct) k = k_batch_score<PT, kModeImageTrilinear, kLayoutOct>;
+    else if (layout == kLayoutOctTile) k = k_batch_score<PT, kModeImageTrilinear, kLayoutOctTile>;
     else k = k_batch_score<PT, kModeImageTrilinear, kLayoutRaw>;
     return reinterpret_cast<ScoreKernel>(k);
 }

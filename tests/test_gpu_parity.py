@@ -281,12 +281,21 @@ def test_tuning_invariance(smc, orc):
     r = _reg(smc, pair, prm, src_fov=pair["src_fov"])
     x = np.vstack([np.zeros(6), _random_states(40, 20, 3, 8)])
     want = _oracle_sums(orc, orc.Volume(pair["src"], fov=pair["src_fov"]), orc.Volume(pair["tgt"]), x, "trilinear")
-    for layout in ("raw", "pairx", "quadxy", "oct"):
+    for layout in ("raw", "pairx", "quadxy", "oct", "octtile"):
         for pt in (4, 8, 16):
             for depth in (7, 32, 256):
                 r.tune(layout, pt, depth)
                 assert r.tuning() == dict(layout=smc.LAYOUTS[layout], particles_per_group=pt, tile_depth=depth)
                 assert np.array_equal(r.evaluate(x), want), (layout, pt, depth)
+    # a source whose x and y extents are not multiples of the 4 x 4 tiles
+    # and differ from each other and from the target's
+    cut = dict(src=np.ascontiguousarray(pair["src"][:29, :34, :35]), tgt=pair["tgt"],
+               src_fov=np.ascontiguousarray(pair["src_fov"][:29, :34, :35]))
+    rc = _reg(smc, cut, prm, src_fov=cut["src_fov"])
+    wc = _oracle_sums(orc, orc.Volume(cut["src"], fov=cut["src_fov"]), orc.Volume(cut["tgt"]), x, "trilinear")
+    for layout in ("raw", "oct", "octtile"):
+        rc.tune(layout, 4, 32)
+        assert np.array_equal(rc.evaluate(x), wc), layout
     mpair = synth.shell_pair(seed=3, side=40)
     m = _reg(smc, mpair, config.default_params("dice", 21, 2, 15.0, 5.0))
     xm = _random_states(21, 15, 5, 9)
@@ -366,7 +375,7 @@ def test_autotune_keeps_results(smc, orc):
     prm = config.default_params("ncc", 64, 2, 20.0, 4.0)
     r = _reg(smc, pair, prm, src_fov=pair["src_fov"])
     t = r.autotune(reps=2)
-    assert t["layout"] in (0, 1, 2, 3) and t["particles_per_group"] in (4, 8) and t["ms"] > 0
+    assert t["layout"] in (0, 1, 2, 3, 4) and t["particles_per_group"] in (4, 8) and t["ms"] > 0
     x = _random_states(20, 20, 4, 23)
     want = _oracle_sums(orc, orc.Volume(pair["src"], fov=pair["src_fov"]), orc.Volume(pair["tgt"]), x, "trilinear")
     assert np.array_equal(r.evaluate(x), want)
@@ -399,6 +408,6 @@ def test_fov_sentinel_and_fallback_exact(smc, orc):
     x[:, 1] = 0.0  # stay within the two slices
     x[:, 5] = 0.0
     want = _oracle_sums(orc, orc.Volume(src, fov=fov), orc.Volume(tgt), x, "trilinear")
-    for layout in ("pairx", "quadxy", "oct", "raw"):
+    for layout in ("pairx", "quadxy", "oct", "octtile", "raw"):
         r.tune(layout, 4, 32)
         assert np.array_equal(r.evaluate(x), want), layout
