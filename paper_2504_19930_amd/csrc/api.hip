@@ -898,8 +898,9 @@ struct smc_batch {
         std::vector<uint32_t> members;
         void *args = nullptr;
         uint32_t *offs = nullptr, *kmax = nullptr, *lists = nullptr;
-    } cls[2];  // 0 masks, 1 trilinear images (other modes run per pair)
-    std::vector<uint32_t> singles;  // pairs outside the two classes
+    } cls[4];  // 0 masks; 1, 2, 3 trilinear images by source FOV validity mode 0, 1, 2
+    std::vector<uint32_t> images;   // all trilinear image pairs
+    std::vector<uint32_t> singles;  // pairs outside the classes (nearest-neighbour images) run per pair
     std::vector<void *> allocs;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -929,9 +930,12 @@ int device_cus() {
     return cus;
 }
 
-// Work list of one class: items of each pair, pairs assigned to the eight
-// XCD lists greedily by work (largest first) so the lists stay balanced.
-smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode) {
+// Work list of one class.  A pair's items run tile by tile with the
+// particle groups fastest; each pair is cut into eight contiguous ranges of
+// items, range x going to XCD x, so every XCD sweeps one eighth of each
+// volume (its L2 holds that part of the source instead of a whole large
+// volume) and the lists stay balanced whatever the mix of pairs.
+smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode, int vmode) {
     const uint32_t n = (uint32_t)C.members.size();
     if (n == 0) return SMC_OK;
     const size_t ab = score_args_bytes();
@@ -950,17 +954,18 @@ smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode) {
         kmax[q] = c->f.n_iters;
         work[q] = (double)items * (double)c->tn[2];
     }
+    // largest pairs first, so the longest runs start early on every XCD
     std::vector<uint32_t> order(n);
     for (uint32_t q = 0; q < n; ++q) order[q] = q;
     std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t c) { return work[a] > work[c]; });
     std::vector<std::vector<uint32_t>> lists(8);
-    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t q : order) {
-        int x = 0;
-        for (int y = 1; y < 8; ++y)
-            if (load[y] < load[x]) x = y;
-        load[x] += work[q];
-        for (uint32_t g = offs[q]; g < offs[q + 1]; ++g) lists[x].push_back(g);
+        const uint32_t items = offs[q + 1] - offs[q];
+        for (uint32_t x = 0; x < 8; ++x) {
+            const uint32_t lo = offs[q] + (uint32_t)((uint64_t)items * x / 8);
+            const uint32_t hi = offs[q] + (uint32_t)((uint64_t)items * (x + 1) / 8);
+            for (uint32_t g = lo; g < hi; ++g) lists[x].push_back(g);
+        }
     }
     std::vector<uint32_t> flat;
     C.plan.list_off[0] = 0;
@@ -979,14 +984,31 @@ smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode) {
     C.plan.mode = mode;
     C.plan.layout = layout;
     C.plan.pt = pt;
+    C.plan.vmode = vmode;
     C.plan.pairs = C.args;
     C.plan.offs = C.offs;
     C.plan.kmax = C.kmax;
     C.plan.lists = C.lists;
     C.plan.n_pairs = n;
-    // persistent grid: a few workgroups per CU, a multiple of the 8 XCDs
-    const uint32_t per_cu = mode == kModeMask ? 6 : 4;
+    // persistent grid: as many workgroups as stay resident, a multiple of the 8 XCDs
+    const uint32_t per_cu = (uint32_t)batch_blocks_per_cu(C.plan);
     C.plan.grid = 8 * (((uint32_t)device_cus() * per_cu + 7) / 8);
+    return SMC_OK;
+}
+
+// Split the image pairs by source FOV validity mode (one kernel variant per
+// class keeps each variant's register budget) and plan every class.
+smc_status plan_all(smc_batch *b) {
+    for (int q = 1; q < 4; ++q) b->cls[q].members.clear();
+    for (uint32_t i : b->images) {
+        smc_ctx *c = b->pairs[i];
+        const int vm = score_vmode(c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true));
+        b->cls[1 + vm].members.push_back(i);
+    }
+    smc_status st;
+    for (int q = 0; q < 4; ++q)
+        if ((st = plan_class(b, b->cls[q], q == 0 ? kModeMask : kModeImageTrilinear, q == 0 ? 0 : q - 1)) != SMC_OK)
+            return st;
     return SMC_OK;
 }
 
@@ -995,7 +1017,7 @@ smc_status record_run(smc_batch *b) {
     HIP_TRY(launch_init_batch(b->states_dev, (uint32_t)b->pairs.size(), b->max_threads, b->stream));
     for (smc_ctx *c : b->pairs) HIP_TRY(launch_fill_u64(c->f.sums, 6ull * (c->f.n + 1), b->stream));
     for (uint32_t k = 1; k <= b->kmax_all; ++k) {
-        for (int q = 0; q < 2; ++q) HIP_TRY(launch_batch_score(b->cls[q].plan, k, b->stream));
+        for (int q = 0; q < 4; ++q) HIP_TRY(launch_batch_score(b->cls[q].plan, k, b->stream));
         for (uint32_t i : b->singles) {
             smc_ctx *c = b->pairs[i];
             if (k <= c->f.n_iters)
@@ -1047,19 +1069,18 @@ smc_status smc_batch_init(smc_batch **out, uint32_t n_pairs, const smc_volume *s
         b->kmax_all = std::max(b->kmax_all, c->f.n_iters);
         b->max_threads = std::max(b->max_threads, std::max(c->f.n, c->f.n_iters + 1));
         if (c->mode == kModeMask) b->cls[0].members.push_back(i);
-        else if (c->mode == kModeImageTrilinear) b->cls[1].members.push_back(i);
+        else if (c->mode == kModeImageTrilinear) b->images.push_back(i);
         else b->singles.push_back(i);
     }
     // one layout / particles-per-group for all trilinear pairs: the first pair's
-    for (uint32_t q = 1; q < b->cls[1].members.size(); ++q) {
-        smc_ctx *c0 = b->pairs[b->cls[1].members[0]], *c = b->pairs[b->cls[1].members[q]];
+    for (uint32_t q = 1; q < b->images.size(); ++q) {
+        smc_ctx *c0 = b->pairs[b->images[0]], *c = b->pairs[b->images[q]];
         if ((st = smc_set_tuning(c, c0->layout, c0->pt, c0->zchunk)) != SMC_OK) return bail(st);
     }
     if ((st = b->alloc(&b->states_dev, n_pairs)) != SMC_OK) return bail(st);
     if (hipMemcpy(b->states_dev, b->states.data(), sizeof(FilterState) * n_pairs, hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(SMC_EDEVICE, "upload of filter states failed"));
-    if ((st = plan_class(b, b->cls[0], kModeMask)) != SMC_OK) return bail(st);
-    if ((st = plan_class(b, b->cls[1], kModeImageTrilinear)) != SMC_OK) return bail(st);
+    if ((st = plan_all(b)) != SMC_OK) return bail(st);
     if (hipStreamSynchronize(b->stream) != hipSuccess) return bail(fail(SMC_EDEVICE, "batch preparation failed"));
     *out = b;
     return SMC_OK;
@@ -1112,11 +1133,11 @@ smc_status smc_batch_autotune(smc_batch *b, uint32_t reps) {
     if (!b) return fail(SMC_EINVAL, "batch is NULL");
     smc_status st;
     for (int q = 0; q < 2; ++q) {
-        auto &C = b->cls[q];
-        if (C.members.empty()) continue;
-        uint32_t big = C.members[0];
+        const std::vector<uint32_t> &members = q == 0 ? b->cls[0].members : b->images;
+        if (members.empty()) continue;
+        uint32_t big = members[0];
         double work = 0.0;
-        for (uint32_t i : C.members) {
+        for (uint32_t i : members) {
             smc_ctx *c = b->pairs[i];
             const double w = (double)c->tn[0] * c->tn[1] * c->tn[2] * (double)(c->f.n + 1);
             if (w > work) {
@@ -1126,10 +1147,10 @@ smc_status smc_batch_autotune(smc_batch *b, uint32_t reps) {
         }
         smc_ctx *c0 = b->pairs[big];
         if ((st = smc_autotune(c0, reps, nullptr)) != SMC_OK) return st;
-        for (uint32_t i : C.members)
+        for (uint32_t i : members)
             if ((st = smc_set_tuning(b->pairs[i], c0->layout, c0->pt, c0->zchunk)) != SMC_OK) return st;
-        if ((st = plan_class(b, C, q == 0 ? kModeMask : kModeImageTrilinear)) != SMC_OK) return st;
     }
+    if ((st = plan_all(b)) != SMC_OK) return st;
     HIP_TRY(hipStreamSynchronize(b->stream));
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);

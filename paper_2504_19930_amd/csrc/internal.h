@@ -60,7 +60,7 @@ uint64_t packed_bytes(int layout, const int32_t n[3]);
 // Batched warp-and-score: one persistent launch over the work items of many
 // pairs of one class (masks, or trilinear images in one layout).
 struct BatchPlan {
-    int mode, layout, pt;
+    int mode, layout, pt, vmode;  // vmode: source FOV validity (0 none, 1 gathered, 2 sentinel)
     const void *pairs;        // device array of per-pair kernel arguments (score_args)
     const uint32_t *offs;     // n_pairs + 1 item offsets
     const uint32_t *kmax;     // iterations per pair
@@ -73,6 +73,11 @@ size_t score_args_bytes();
 uint32_t score_items(const ScoreLaunch &L);
 void score_args(const ScoreLaunch &L, void *out);
 hipError_t launch_batch_score(const BatchPlan &P, uint32_t k, hipStream_t s);
+const void *batch_kernel(const BatchPlan &P);
+// resident workgroups per CU of the plan's kernel (the persistent grid size)
+int batch_blocks_per_cu(const BatchPlan &P);
+// source FOV validity mode of a launch: 0 none, 1 gathered mask, 2 sentinel
+int score_vmode(const ScoreLaunch &L);
 
 // Preparation of inputs.
 hipError_t launch_prep_mask(const uint8_t *vol, const uint8_t *fov, uint8_t *out, int64_t n, hipStream_t s);

@@ -70,6 +70,20 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     return v;
 }
 
+// Data that no kernel of a launch writes (recipe words, batch arguments,
+// lists and offsets) is read through the constant address space, so the
+// compiler can use scalar loads and scalar registers for uniform reads.
+// (the address space exists only in the device compilation)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SMC_CONSTANT_AS __attribute__((address_space(4)))
+#else
+#define SMC_CONSTANT_AS
+#endif
+template <typename T>
+__device__ __forceinline__ const SMC_CONSTANT_AS T *as_const(const T *p) {
+    return (const SMC_CONSTANT_AS T *)p;
+}
+
 struct Tile {
     int i, j, k0, k1;
     bool ok;
@@ -110,7 +124,7 @@ __device__ __forceinline__ void column_terms(const KArgs &a, const Tile &t, floa
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
         const uint32_t q = min(t.pbase + (uint32_t)p, last);
-        const float *w = a.words + 12 * (size_t)q;
+        const auto *w = as_const(a.words) + 12 * (size_t)q;
         mx[p] = fmaf(w[1], fj, fmaf(w[0], fi, w[3]));
         my[p] = fmaf(w[5], fj, fmaf(w[4], fi, w[7]));
         mz[p] = fmaf(w[9], fj, fmaf(w[8], fi, w[11]));
@@ -136,7 +150,7 @@ __device__ __forceinline__ uint32_t live_mask(const KArgs &a, const Tile &t, uin
     uint32_t live = 0;
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
-        const float *w = a.words + 12 * (size_t)min(t.pbase + (uint32_t)p, last);
+        const auto *w = as_const(a.words) + 12 * (size_t)min(t.pbase + (uint32_t)p, last);
         bool ok = p < t.npg;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -635,7 +649,8 @@ struct BatchArgs {
     uint32_t k;                // iteration being scored (pairs with kmax < k are done)
 };
 
-__device__ __forceinline__ uint32_t pair_of(const uint32_t *offs, uint32_t n, uint32_t g) {
+__device__ __forceinline__ uint32_t pair_of(const uint32_t *offs_g, uint32_t n, uint32_t g) {
+    const auto *offs = as_const(offs_g);
     uint32_t lo = 0, hi = n - 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) >> 1;
@@ -645,27 +660,23 @@ __device__ __forceinline__ uint32_t pair_of(const uint32_t *offs, uint32_t n, ui
     return lo;
 }
 
-template <int PT, int MODE, int LAYOUT>
+template <int PT, int MODE, int LAYOUT, int VMODE>
 __global__ __launch_bounds__(kThreads) void k_batch_score(const BatchArgs b) {
     const uint32_t x = blockIdx.x % 8, per = gridDim.x / 8 + ((blockIdx.x % 8) < gridDim.x % 8 ? 1u : 0u);
     const uint32_t begin = b.list_off[x], end = b.list_off[x + 1];
+    const auto *lists = as_const(b.lists);
+    const auto *kmax = as_const(b.kmax);
+    const auto *pairs = as_const(b.pairs);
     for (uint32_t q = begin + blockIdx.x / 8; q < end; q += per) {
-        const uint32_t g = b.lists[q];
+        const uint32_t g = lists[q];
         const uint32_t d = pair_of(b.offs, b.n_pairs, g);
-        if (b.kmax[d] < b.k) continue;
-        const KArgs &a = b.pairs[d];
+        if (kmax[d] < b.k) continue;
+        const KArgs a = pairs[d];
         const uint32_t local = g - b.offs[d];
         const uint32_t ng = (a.np + PT - 1) / PT;
         const uint32_t bx = local / ng, by = local - bx * ng;
-        if (MODE == kModeMask) {
-            mask_body<PT>(a, bx, by);
-        } else if (a.vmode == 2 && LAYOUT != kLayoutRaw) {
-            image_body<PT, LAYOUT, true, 2>(a, bx, by);
-        } else if (a.vmode != 0) {
-            image_body<PT, LAYOUT, true, 1>(a, bx, by);
-        } else {
-            image_body<PT, LAYOUT, true, 0>(a, bx, by);
-        }
+        if (MODE == kModeMask) mask_body<PT>(a, bx, by);
+        else image_body<PT, LAYOUT, true, VMODE>(a, bx, by);
         __syncthreads();
     }
 }
@@ -727,7 +738,9 @@ typedef void (*ScoreKernel)(const KArgs);
 
 template <int PT, int LAYOUT>
 ScoreKernel pick_tri(int vmode) {
-    if (vmode == 2 && LAYOUT != kLayoutRaw) return k_score_image<PT, LAYOUT, true, 2>;
+    if constexpr (LAYOUT != kLayoutRaw) {
+        if (vmode == 2) return k_score_image<PT, LAYOUT, true, 2>;
+    }
     return vmode ? k_score_image<PT, LAYOUT, true, 1> : k_score_image<PT, LAYOUT, true, 0>;
 }
 
@@ -777,17 +790,33 @@ void score_args(const ScoreLaunch &L, void *out) {
 }
 
 namespace {
-template <int PT>
-ScoreKernel pick_batch(int mode, int layout) {
+template <int PT, int LAYOUT>
+ScoreKernel pick_batch_image(int vmode) {
     typedef void (*BK)(const BatchArgs);
     BK k;
-    if (mode == kModeMask) k = k_batch_score<PT, kModeMask, kLayoutRaw>;
-    else if (layout == kLayoutPairX) k = k_batch_score<PT, kModeImageTrilinear, kLayoutPairX>;
-    else if (layout == kLayoutQuadXY) k = k_batch_score<PT, kModeImageTrilinear, kLayoutQuadXY>;
-    else if (layout == kLayoutOct) k = k_batch_score<PT, kModeImageTrilinear, kLayoutOct>;
-    else if (layout == kLayoutOctTile) k = k_batch_score<PT, kModeImageTrilinear, kLayoutOctTile>;
-    else k = k_batch_score<PT, kModeImageTrilinear, kLayoutRaw>;
+    if constexpr (LAYOUT != kLayoutRaw) {
+        if (vmode == 2) return reinterpret_cast<ScoreKernel>(k_batch_score<PT, kModeImageTrilinear, LAYOUT, 2>);
+    }
+    if (vmode != 0) k = k_batch_score<PT, kModeImageTrilinear, LAYOUT, 1>;
+    else k = k_batch_score<PT, kModeImageTrilinear, LAYOUT, 0>;
     return reinterpret_cast<ScoreKernel>(k);
+}
+
+template <int PT>
+ScoreKernel pick_batch(int mode, int layout, int vmode) {
+    if (mode == kModeMask) return reinterpret_cast<ScoreKernel>(k_batch_score<PT, kModeMask, kLayoutRaw, 0>);
+    switch (layout) {
+    case kLayoutPairX: return pick_batch_image<PT, kLayoutPairX>(vmode);
+    case kLayoutQuadXY: return pick_batch_image<PT, kLayoutQuadXY>(vmode);
+    case kLayoutOct: return pick_batch_image<PT, kLayoutOct>(vmode);
+    case kLayoutOctTile: return pick_batch_image<PT, kLayoutOctTile>(vmode);
+    default: return pick_batch_image<PT, kLayoutRaw>(vmode);
+    }
+}
+
+template <int PT>
+ScoreKernel pick_batch_pt(const BatchPlan &P) {
+    return pick_batch<PT>(P.mode, P.layout, P.vmode);
 }
 }  // namespace
 
@@ -802,13 +831,29 @@ hipError_t launch_batch_score(const BatchPlan &P, uint32_t k, hipStream_t s) {
     b.n_pairs = P.n_pairs;
     b.k = k;
     typedef void (*BK)(const BatchArgs);
-    BK kern;
-    const int pt = score_pt_supported(P.pt) ? P.pt : 8;
-    if (pt == 4) kern = reinterpret_cast<BK>(pick_batch<4>(P.mode, P.layout));
-    else if (pt == 16) kern = reinterpret_cast<BK>(pick_batch<16>(P.mode, P.layout));
-    else kern = reinterpret_cast<BK>(pick_batch<8>(P.mode, P.layout));
+    BK kern = reinterpret_cast<BK>(const_cast<void *>(batch_kernel(P)));
     hipLaunchKernelGGL(kern, dim3(P.grid), dim3(kThreads), 0, s, b);
     return hipGetLastError();
+}
+
+const void *batch_kernel(const BatchPlan &P) {
+    const int pt = score_pt_supported(P.pt) ? P.pt : 8;
+    if (pt == 4) return reinterpret_cast<const void *>(pick_batch_pt<4>(P));
+    if (pt == 16) return reinterpret_cast<const void *>(pick_batch_pt<16>(P));
+    return reinterpret_cast<const void *>(pick_batch_pt<8>(P));
+}
+
+int batch_blocks_per_cu(const BatchPlan &P) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel(P), kThreads, 0) != hipSuccess ||
+        blocks < 1)
+        blocks = 4;
+    return blocks;
+}
+
+int score_vmode(const ScoreLaunch &L) {
+    int chunks;
+    return make_args(L, 8, &chunks).vmode;
 }
 
 void score_grid(const ScoreLaunch &L, dim3 *grid, dim3 *block) {
