@@ -47,7 +47,7 @@ class _Params(C.Structure):
                 ("fp64_mode", C.c_int32), ("x0", C.c_double * 6), ("limit", C.c_double * 6),
                 ("sigma_score", C.c_double), ("sigma0", C.c_double * 6), ("anneal", C.c_double),
                 ("min_overlap_frac", C.c_double), ("has_proposal", C.c_int32), ("prop_mu", C.c_double * 6),
-                ("prop_sigma", C.c_double * 6)]
+                ("prop_sigma", C.c_double * 6), ("wide_rotation", C.c_int32)]
 
 
 class _Problem(C.Structure):
@@ -85,6 +85,10 @@ def lib():
             "or_score_particles": (None, [P(_Problem), P(_Params), C.c_uint32, d, d]),
             "or_loglik": (C.c_double, [C.c_double, C.c_int, C.c_double]),
             "or_normalise": (C.c_int, [C.c_uint32, d, d, d, d, P(C.c_double)]),
+            "or_normalise_wide": (C.c_int, [C.c_uint32, d, d, d, d, d, P(C.c_double)]),
+            "or_euler_quat": (None, [d, d]),
+            "or_quat_R": (None, [d, d]),
+            "or_R_euler": (None, [d, d]),
             "or_resample": (None, [C.c_uint32, d, C.c_uint32, i32]),
             "or_gauss6": (None, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, d]),
             "or_perturb": (None, [P(_Params), C.c_uint32, d, i32, d]),
@@ -150,6 +154,7 @@ def make_params(p: dict, fp64_mode: bool = False) -> _Params:
     out.sigma0[:] = [float(v) for v in p["sigma0"]]
     out.anneal = float(p.get("anneal", 0.9))
     out.min_overlap_frac = float(p.get("min_overlap_frac", 0.05))
+    out.wide_rotation = 1 if p.get("rotation_mode", "box") == "wide" else 0
     prop = p.get("proposal")
     if prop is not None:
         out.has_proposal = 1
@@ -262,6 +267,35 @@ def normalise(lw, x):
     ess = C.c_double()
     deg = lib().or_normalise(len(lw), lw, x, w, est, C.byref(ess))
     return dict(w=w, est=est, ess=ess.value, degenerate=bool(deg))
+
+
+def normalise_wide(lw, x, x0):
+    """Normalisation with the quaternion-mean rotation of the wide mode."""
+    lw = np.ascontiguousarray(lw, float)
+    x = np.ascontiguousarray(x, float).reshape(-1, 6)
+    w = np.zeros(len(lw))
+    est = np.zeros(6)
+    ess = C.c_double()
+    deg = lib().or_normalise_wide(len(lw), lw, x, np.ascontiguousarray(x0, float), w, est, C.byref(ess))
+    return dict(w=w, est=est, ess=ess.value, degenerate=bool(deg))
+
+
+def euler_quat(p) -> np.ndarray:
+    q = np.zeros(4)
+    lib().or_euler_quat(np.ascontiguousarray(np.resize(np.asarray(p, float), 6)), q)
+    return q
+
+
+def quat_R(q) -> np.ndarray:
+    R = np.zeros(9)
+    lib().or_quat_R(np.ascontiguousarray(q, float), R)
+    return R.reshape(3, 3)
+
+
+def R_euler(R) -> np.ndarray:
+    e = np.zeros(3)
+    lib().or_R_euler(np.ascontiguousarray(R, float).reshape(9), e)
+    return e
 
 
 def resample(w, u32) -> np.ndarray:

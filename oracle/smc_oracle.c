@@ -147,6 +147,66 @@ void or_euler_R(const double p[6], double R[9])
     matmul3(zx, ry, R);
 }
 
+/* ---- rotations as unit quaternions (w, x, y, z), for the wide-rotation mode */
+
+/* Hamilton product a * b. */
+static void quat_mul(const double a[4], const double b[4], double out[4])
+{
+    out[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    out[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    out[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    out[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+
+/* Quaternion of R = Rz(rz) Rx(rx) Ry(ry): qz * qx * qy, each elementary
+ * rotation by angle a about axis e being (cos a/2, sin a/2 e). */
+void or_euler_quat(const double p[6], double q[4])
+{
+    double qx[4] = {cos(0.5 * p[0]), sin(0.5 * p[0]), 0.0, 0.0};
+    double qy[4] = {cos(0.5 * p[1]), 0.0, sin(0.5 * p[1]), 0.0};
+    double qz[4] = {cos(0.5 * p[2]), 0.0, 0.0, sin(0.5 * p[2])};
+    double zx[4];
+    quat_mul(qz, qx, zx);
+    quat_mul(zx, qy, q);
+}
+
+/* Rotation matrix (row major) of a unit quaternion. */
+void or_quat_R(const double q[4], double R[9])
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+/* Euler angles of R = Rz(rz) Rx(rx) Ry(ry).  Its bottom row is
+ * (-cos rx sin ry, sin rx, cos rx cos ry) and its middle column
+ * (-sin rz cos rx, cos rz cos rx, sin rx), so rx = asin(R21) in
+ * [-pi/2, pi/2], ry = atan2(-R20, R22), rz = atan2(-R01, R11). */
+void or_R_euler(const double R[9], double e[3])
+{
+    double s = R[7];
+    if (s > 1.0) s = 1.0;
+    if (s < -1.0) s = -1.0;
+    e[0] = asin(s);
+    e[1] = atan2(-R[6], R[8]);
+    e[2] = atan2(-R[1], R[4]);
+}
+
+/* The angle equal to a modulo 2 pi in [c - pi, c + pi). */
+static double wrap_near(double a, double c)
+{
+    const double two_pi = 6.283185307179586;
+    double t = a - c + 3.141592653589793;
+    return c + (t - two_pi * floor(t / two_pi)) - 3.141592653589793;
+}
+
 /* Target centre in mm: c_d = (0.5 * s_d) * (n_d - 1). */
 static void centre(const int32_t n[3], const double s[3], double c[3])
 {
@@ -483,6 +543,9 @@ typedef struct {
     /* learned proposal: prior from N(prop_mu, prop_sigma^2) truncated to the box */
     int32_t has_proposal;
     double prop_mu[6], prop_sigma[6];
+    /* 1: wide rotations -- quaternion-mean estimate, and rotation axes whose
+     * limit reaches pi wrap around the circle in the prediction */
+    int32_t wide_rotation;
 } or_params;
 
 typedef struct {
@@ -590,6 +653,41 @@ int or_normalise(uint32_t n, const double *lw, const double *x, double *w, doubl
     return degenerate;
 }
 
+/* Normalisation as or_normalise, with the rotation of the estimate taken
+ * from unit quaternions (wide-rotation mode): the particle quaternions are
+ * put on the hemisphere of the first particle of largest log-weight, summed
+ * with their weights and normalised (the weighted chordal mean to first order
+ * in the spread, independent of how angles wrap); the Euler angles of that
+ * rotation are then moved by whole turns to lie within pi of x0. */
+int or_normalise_wide(uint32_t n, const double *lw, const double *x, const double x0[6], double *w, double est[6],
+                      double *ess)
+{
+    int degenerate = or_normalise(n, lw, x, w, est, ess);
+    double mx = -INFINITY;
+    uint32_t ref = 0;
+    for (uint32_t i = 0; i < n; ++i)
+        if (lw[i] > mx) {
+            mx = lw[i];
+            ref = i;
+        }
+    double qr[4], acc[4] = {0.0, 0.0, 0.0, 0.0};
+    or_euler_quat(x + 6 * (size_t)ref, qr);
+    for (uint32_t i = 0; i < n; ++i) {
+        double q[4];
+        or_euler_quat(x + 6 * (size_t)i, q);
+        double dot = q[0] * qr[0] + q[1] * qr[1] + q[2] * qr[2] + q[3] * qr[3];
+        double sgn = dot < 0.0 ? -1.0 : 1.0;
+        for (int c = 0; c < 4; ++c) acc[c] += (w[i] * sgn) * q[c];
+    }
+    double nrm = sqrt(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2] + acc[3] * acc[3]);
+    double q[4], R[9], e[3];
+    for (int c = 0; c < 4; ++c) q[c] = acc[c] / nrm;
+    or_quat_R(q, R);
+    or_R_euler(R, e);
+    for (int d = 0; d < 3; ++d) est[d] = wrap_near(e[d], x0[d]);
+    return degenerate;
+}
+
 /* Systematic resampling on an exact integer CDF.  q_i = floor(w_i 2^48),
  * Q = sum q_i, C_i the inclusive prefix sums; with one uniform word U the
  * j-th pointer is (j + U / 2^32) Q / N and the ancestor of j is the first i
@@ -648,7 +746,9 @@ static double sigma_k(const or_params *pr, int d, uint32_t k)
     return s;
 }
 
-/* Prediction: x_j = reflect(x_{a_j} + sigma_k g_j). */
+/* Prediction: x_j = reflect(x_{a_j} + sigma_k g_j); in the wide-rotation mode
+ * a rotation axis whose limit reaches pi wraps into [x0 - pi, x0 + pi)
+ * instead (the box is then the whole circle). */
 void or_perturb(const or_params *pr, uint32_t k, const double *x_old, const int32_t *anc, double *x_new)
 {
     double lo[6], hi[6], sg[6];
@@ -660,8 +760,13 @@ void or_perturb(const or_params *pr, uint32_t k, const double *x_old, const int3
     for (uint32_t j = 0; j < pr->n_particles; ++j) {
         double g[6];
         or_gauss6(pr->seed, pr->pair_id, j, k, g);
-        for (int d = 0; d < 6; ++d)
-            x_new[6 * (size_t)j + d] = reflect(x_old[6 * (size_t)anc[j] + d] + sg[d] * g[d], lo[d], hi[d]);
+        for (int d = 0; d < 6; ++d) {
+            double v = x_old[6 * (size_t)anc[j] + d] + sg[d] * g[d];
+            if (pr->wide_rotation && d < 3 && pr->limit[d] >= 3.141592653589793)
+                x_new[6 * (size_t)j + d] = wrap_near(v, pr->x0[d]);
+            else
+                x_new[6 * (size_t)j + d] = reflect(v, lo[d], hi[d]);
+        }
     }
 }
 
@@ -749,7 +854,8 @@ int or_filter_update(const or_params *pr, uint32_t k, const double *x, const dou
         /* importance correction of the proposal draw: log p - log q, p uniform */
         if (k == 1 && pr->has_proposal && lq) lw[i] = lw[i] + lq[i];
     }
-    int degen = or_normalise(n, lw, x, w, est, ess);
+    int degen = pr->wide_rotation ? or_normalise_wide(n, lw, x, pr->x0, w, est, ess)
+                                  : or_normalise(n, lw, x, w, est, ess);
     if (k < pr->n_iters) {
         or_resample(n, w, or_resample_word(pr, k), anc);
         or_perturb(pr, k, x, anc, x_next);
