@@ -53,6 +53,17 @@ typedef enum { SMC_SCORE_DICE = 0, SMC_SCORE_NCC = 1, SMC_SCORE_SSD = 2 } smc_sc
  * trilinear interpolation).  DICE requires NEAREST. */
 typedef enum { SMC_INTERP_NEAREST = 0, SMC_INTERP_TRILINEAR = 1 } smc_interp;
 
+/* How rotations are treated (the paper's own search is the BOX: Euler angles
+ * in x0 +- limit, weighted-mean estimate).  WIDE is for searches whose
+ * rotation limits reach a half turn (views far apart, e.g. apical against
+ * parasternal): the estimate's rotation is the normalised weighted sum of the
+ * particles' unit quaternions, put on the hemisphere of the first particle of
+ * largest weight, converted back to Euler angles within pi of x0; and every
+ * rotation axis whose limit is >= pi wraps around the circle in the
+ * prediction instead of reflecting.  Axes with smaller limits, the
+ * translations, the prior and the weights are as in BOX. */
+typedef enum { SMC_ROTATION_BOX = 0, SMC_ROTATION_WIDE = 1 } smc_rotation;
+
 typedef struct {
     int32_t nx, ny, nz;      /* voxels, each >= 1 */
     double sx, sy, sz;       /* spacing in mm, > 0 */
@@ -76,6 +87,7 @@ typedef struct {
     double sigma0[6];        /* random-walk width of the first prediction, >= 0 */
     double anneal;           /* width factor per iteration, 0 < anneal <= 1 */
     double min_overlap_frac; /* NCC / SSD: overlaps under this fraction of the target FOV get weight 0 */
+    int32_t rotation_mode;   /* smc_rotation */
 } smc_params;
 
 typedef struct smc_ctx smc_ctx;

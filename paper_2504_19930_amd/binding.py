@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(PKG, "libsmc.so")
 SMC_OK, SMC_EINVAL, SMC_ENOMEM, SMC_EDEVICE, SMC_ESTATE = 0, -1, -2, -3, -4
 SCORES = {"dice": 0, "ncc": 1, "ssd": 2}
 INTERPS = {"nearest": 0, "trilinear": 1}
+ROTATIONS = {"box": 0, "wide": 1}
 
 # every symbol include/smc.h declares
 EXPORTS = ("smc_init", "smc_reset", "smc_step", "smc_estimate", "smc_get_particles", "smc_trace",
@@ -48,7 +49,8 @@ class SmcParams(C.Structure):
     _fields_ = [("n_particles", C.c_uint32), ("n_iters", C.c_uint32), ("seed", C.c_uint64),
                 ("pair_id", C.c_uint32), ("score", C.c_int32), ("interp", C.c_int32),
                 ("x0", C.c_double * 6), ("limit", C.c_double * 6), ("sigma_score", C.c_double),
-                ("sigma0", C.c_double * 6), ("anneal", C.c_double), ("min_overlap_frac", C.c_double)]
+                ("sigma0", C.c_double * 6), ("anneal", C.c_double), ("min_overlap_frac", C.c_double),
+                ("rotation_mode", C.c_int32)]
 
 
 _lib = None
@@ -158,6 +160,7 @@ def params(p: dict) -> SmcParams:
     out.sigma0[:] = [float(v) for v in p["sigma0"]]
     out.anneal = float(p.get("anneal", 0.85))
     out.min_overlap_frac = float(p.get("min_overlap_frac", 0.05))
+    out.rotation_mode = ROTATIONS[p.get("rotation_mode", "box")]
     return out
 
 

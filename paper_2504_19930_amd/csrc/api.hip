@@ -72,6 +72,8 @@ smc_status check_params(const smc_params *p) {
     if (p->score < SMC_SCORE_DICE || p->score > SMC_SCORE_SSD) return fail(SMC_EINVAL, "unknown score %d", p->score);
     if (p->interp != SMC_INTERP_NEAREST && p->interp != SMC_INTERP_TRILINEAR)
         return fail(SMC_EINVAL, "unknown interpolation %d", p->interp);
+    if (p->rotation_mode != SMC_ROTATION_BOX && p->rotation_mode != SMC_ROTATION_WIDE)
+        return fail(SMC_EINVAL, "unknown rotation_mode %d", p->rotation_mode);
     if (p->score == SMC_SCORE_DICE && p->interp != SMC_INTERP_NEAREST)
         return fail(SMC_EINVAL, "the Dice score works on binary masks with nearest-neighbour sampling");
     if (!finite6(p->x0) || !finite6(p->limit) || !finite6(p->sigma0))
@@ -428,6 +430,7 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
         f.sigma0[d] = p->sigma0[d];
     }
     f.anneal = p->anneal;
+    f.wide = p->rotation_mode == SMC_ROTATION_WIDE ? 1 : 0;
     if ((st = c->alloc(&f.x, 6ull * n)) != SMC_OK ||
         (st = c->alloc(&f.x_next, 6ull * n)) != SMC_OK ||
         (st = c->alloc(&f.words, 12ull * (n + 1))) != SMC_OK ||

@@ -180,6 +180,40 @@ SMC_HD double log_likelihood(double z, const ScoreConst &sc) {
     return -(d * d) * (0.5 / (sc.sigma * sc.sigma));
 }
 
+// ---- wide rotations: unit quaternions (w, x, y, z)
+
+// Quaternion of R = Rz(p2) Rx(p0) Ry(p1): the product of the half-angle
+// quaternions qz qx qy, written out (qz qx has no zero component).
+SMC_HD void rotation_quaternion(const double p[6], double q[4]) {
+    const double ca = cos(0.5 * p[0]), sa = sin(0.5 * p[0]);
+    const double cb = cos(0.5 * p[1]), sb = sin(0.5 * p[1]);
+    const double cc = cos(0.5 * p[2]), sc = sin(0.5 * p[2]);
+    const double zx[4] = {cc * ca, cc * sa, sc * sa, sc * ca};
+    q[0] = zx[0] * cb - zx[2] * sb;
+    q[1] = zx[1] * cb - zx[3] * sb;
+    q[2] = zx[0] * sb + zx[2] * cb;
+    q[3] = zx[1] * sb + zx[3] * cb;
+}
+
+// Euler angles (p0, p1, p2) of the rotation of a unit quaternion, for
+// R = Rz(p2) Rx(p0) Ry(p1): p0 = asin(R21), p1 = atan2(-R20, R22),
+// p2 = atan2(-R01, R11), from the entries of the quaternion's matrix.
+SMC_HD void quaternion_euler(const double q[4], double e[3]) {
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    const double r01 = 2.0 * (x * y - w * z), r11 = 1.0 - 2.0 * (x * x + z * z);
+    const double r20 = 2.0 * (x * z - w * y), r21 = 2.0 * (y * z + w * x), r22 = 1.0 - 2.0 * (x * x + y * y);
+    e[0] = asin(fmin(1.0, fmax(-1.0, r21)));
+    e[1] = atan2(-r20, r22);
+    e[2] = atan2(-r01, r11);
+}
+
+// a moved by whole turns into [c - pi, c + pi)
+SMC_HD double wrap_near(double a, double c) {
+    const double pi = 3.141592653589793, turn = 6.283185307179586;
+    const double t = a - c + pi;
+    return c + (t - turn * floor(t / turn)) - pi;
+}
+
 SMC_HD double reflect_into(double v, double lo, double hi) {
     if (v < lo) v = lo + (lo - v);
     if (v > hi) v = hi - (v - hi);

@@ -20,6 +20,11 @@ __device__ __forceinline__ double wave_max(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
 }
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
+    return v;
+}
+
 __device__ __forceinline__ double wave_add(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -125,8 +130,9 @@ __device__ __forceinline__ bool pointer_passed(unsigned long long c, unsigned __
 }
 
 __device__ __forceinline__ void filter_body(const FilterState &f, const uint32_t k) {
-    __shared__ double red[kFW][8];
-    __shared__ double bcast[8];
+    __shared__ double red[kFW][12];
+    __shared__ double bcast[12];
+    __shared__ uint32_t ref_idx[kFW];
     __shared__ unsigned long long scan[kFT];
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const uint32_t n = f.n;
@@ -158,26 +164,54 @@ __device__ __forceinline__ void filter_body(const FilterState &f, const uint32_t
     const double M = bcast[0];
     const bool degenerate = M == -INFINITY;
 
-    // normalise and estimate: w_i = exp(lw_i - M), weighted mean, ESS
-    double s = 0.0, s2 = 0.0, sx[6] = {0, 0, 0, 0, 0, 0};
+    // wide rotations: the reference hemisphere is that of the first particle
+    // of largest log-weight (all of them when every weight is -inf)
+    double qref[4] = {1.0, 0.0, 0.0, 0.0};
+    if (f.wide) {
+        uint32_t first = n;
+        for (uint32_t i = tid; i < n; i += kFT)
+            if (f.lw[i] == M) {
+                first = i;
+                break;
+            }
+        first = wave_min_u32(first);
+        if (lane == 0) ref_idx[wave] = first;
+        __syncthreads();
+        uint32_t r = ref_idx[0];
+        for (int w = 1; w < kFW; ++w) r = min(r, ref_idx[w]);
+        rotation_quaternion(f.x + 6 * (size_t)(r < n ? r : 0u), qref);
+    }
+
+    // normalise and estimate: w_i = exp(lw_i - M), weighted mean, ESS, and
+    // for wide rotations the weighted sum of hemisphere-aligned quaternions
+    double s = 0.0, s2 = 0.0, sx[6] = {0, 0, 0, 0, 0, 0}, sq[4] = {0, 0, 0, 0};
     for (uint32_t i = tid; i < n; i += kFT) {
         const double w = degenerate ? 1.0 : exp(f.lw[i] - M);
         f.w[i] = w;
         s += w;
         s2 += w * w;
         for (int d = 0; d < 6; ++d) sx[d] += w * f.x[6 * (size_t)i + d];
+        if (f.wide) {
+            double q[4];
+            rotation_quaternion(f.x + 6 * (size_t)i, q);
+            const double dot = q[0] * qref[0] + q[1] * qref[1] + q[2] * qref[2] + q[3] * qref[3];
+            const double ws = dot < 0.0 ? -w : w;
+            for (int c = 0; c < 4; ++c) sq[c] += ws * q[c];
+        }
     }
     s = wave_add(s);
     s2 = wave_add(s2);
     for (int d = 0; d < 6; ++d) sx[d] = wave_add(sx[d]);
+    for (int c = 0; c < 4; ++c) sq[c] = wave_add(sq[c]);
     __syncthreads();
     if (lane == 0) {
         red[wave][0] = s;
         red[wave][1] = s2;
         for (int d = 0; d < 6; ++d) red[wave][2 + d] = sx[d];
+        for (int c = 0; c < 4; ++c) red[wave][8 + c] = sq[c];
     }
     __syncthreads();
-    if (tid < 8) {
+    if (tid < 12) {
         double v = 0.0;
         for (int w = 0; w < kFW; ++w) v += red[w][tid];
         bcast[tid] = v;
@@ -185,8 +219,16 @@ __device__ __forceinline__ void filter_body(const FilterState &f, const uint32_t
     __syncthreads();
     if (tid == 0) {
         double est[6];
+        for (int d = 0; d < 6; ++d) est[d] = bcast[2 + d] / bcast[0];
+        if (f.wide) {
+            const double nq = sqrt(bcast[8] * bcast[8] + bcast[9] * bcast[9] + bcast[10] * bcast[10] +
+                                   bcast[11] * bcast[11]);
+            const double q[4] = {bcast[8] / nq, bcast[9] / nq, bcast[10] / nq, bcast[11] / nq};
+            double e[3];
+            quaternion_euler(q, e);
+            for (int d = 0; d < 3; ++d) est[d] = wrap_near(e[d], f.x0[d]);
+        }
         for (int d = 0; d < 6; ++d) {
-            est[d] = bcast[2 + d] / bcast[0];
             f.est[d] = est[d];
             f.trace_est[6 * (size_t)(k - 1) + d] = est[d];
         }
@@ -246,8 +288,13 @@ __device__ __forceinline__ void filter_body(const FilterState &f, const uint32_t
                 g[2 * b] = rad * cos(th);
                 g[2 * b + 1] = rad * sin(th);
             }
-            for (int d = 0; d < 6; ++d)
-                f.x_next[6 * (size_t)j + d] = reflect_into(f.x[6 * (size_t)lo + d] + sg[d] * g[d], f.lo[d], f.hi[d]);
+            for (int d = 0; d < 6; ++d) {
+                const double v = f.x[6 * (size_t)lo + d] + sg[d] * g[d];
+                // wide rotations: an axis whose limit covers the circle wraps
+                f.x_next[6 * (size_t)j + d] = f.wide && d < 3 && f.limit[d] >= 3.141592653589793
+                                                  ? wrap_near(v, f.x0[d])
+                                                  : reflect_into(v, f.lo[d], f.hi[d]);
+            }
         }
         __syncthreads();
         for (uint32_t j = tid; j < n; j += kFT) {

@@ -117,6 +117,8 @@ struct FilterState {
     int32_t has_proposal;
     double prop_mu[6], prop_sigma[6];
     double *lq;               // n: -log q(x_i) + const of the proposal draw
+    // wide rotations: quaternion-mean estimate; rotation axes with limit >= pi wrap
+    int32_t wide;
 };
 
 hipError_t launch_init_particles(const FilterState &f, hipStream_t s);

@@ -166,6 +166,26 @@ def test_full_filter_image_ncc_and_ssd(smc, orc):
         _compare_runs(smc, orc, pair, prm, src_fov=pair["src_fov"])
 
 
+def test_wide_rotation_filter_matches_oracle(smc, orc):
+    """Wide-rotation mode: an off-centre ellipsoid turned by 178 degrees
+    about z, rz searched over the whole circle (wrapped prediction), and an
+    NCC image pair with limits below a half turn (quaternion-mean estimate
+    only); same ancestors, states and estimates as the oracle."""
+    import math
+    gt = np.array([math.radians(4.0), math.radians(-3.0), math.radians(178.0), 2.0, -1.5, 1.0])
+    pair = synth.mask_pair((40, 40, 40), outer=(10.0, 7.0, 5.0), inner=None, gt=gt,
+                           centre=(26.5, 22.5, 21.5))
+    prm = config.default_params("dice", 512, 15, 10.0, 4.0, seed=5)
+    prm["limit"][2] = math.pi
+    prm["sigma0"][2] = 0.075
+    prm["rotation_mode"] = "wide"
+    r, o = _compare_runs(smc, orc, pair, prm)
+    assert np.all(np.abs(r.particles()["states"][:, 2]) <= math.pi)
+    img = synth.speckle_pair(side=40, seed=9, trans=3.0)
+    prm = dict(config.default_params("ncc", 192, 5, 20.0, 3.0, seed=4), rotation_mode="wide")
+    _compare_runs(smc, orc, img, prm, src_fov=img["src_fov"])
+
+
 def test_degenerate_sizes(smc, orc):
     pair = synth.shell_pair(seed=2, side=24)
     _compare_runs(smc, orc, pair, config.default_params("dice", 1, 3, 15.0, 3.0, seed=3))

@@ -97,3 +97,28 @@ def test_binding_refuses_host_tensors(smc):
     import torch
     with pytest.raises(ValueError):
         smc.volume(torch.zeros((4, 4, 4), dtype=torch.uint8))
+
+
+def test_struct_layouts_match_the_header(smc, tmp_path):
+    """The ctypes mirrors of smc_volume and smc_params have the sizes and
+    field offsets the C compiler gives the header's structs."""
+    import subprocess
+    prog = tmp_path / "layout.c"
+    prog.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "smc.h"\n'
+                    'int main(void) { printf("%zu %zu %zu %zu %zu\\n", sizeof(smc_volume), sizeof(smc_params), '
+                    'offsetof(smc_params, min_overlap_frac), offsetof(smc_params, rotation_mode), '
+                    'offsetof(smc_volume, fov)); return 0; }\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [C.sizeof(smc.SmcVolume), C.sizeof(smc.SmcParams), smc.SmcParams.min_overlap_frac.offset,
+            smc.SmcParams.rotation_mode.offset, smc.SmcVolume.fov.offset]
+    assert got == want
+
+
+def test_unknown_rotation_mode_rejected(smc):
+    prm = _params(smc)
+    prm.rotation_mode = 2
+    st, _ = _init_status(smc, _vol(smc), _vol(smc), prm)
+    assert st == smc.SMC_EINVAL
+    assert "rotation_mode" in smc.lib().smc_last_error().decode()
