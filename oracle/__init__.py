@@ -98,6 +98,9 @@ def lib():
                                            d]),
             "or_init_proposal": (None, [P(_Params), d, d]),
             "or_smc_run": (C.c_int, [P(_Vol), P(_Vol), P(_Params), d, d, d, d, d, d, i32]),
+            "or_smc_run_frames": (C.c_int, [P(_Vol), P(_Vol), C.c_uint32, P(_Params), d, d, d, d, d, d, i32]),
+            "or_frame_sums": (None, [P(_Problem), C.c_uint32, P(_Params), d, i64]),
+            "or_score_particle_frames": (C.c_double, [P(_Problem), C.c_uint32, P(_Params), d]),
             "or_warp_apply": (None, [P(_Vol), d, C.c_int, u8, C.c_int32, C.c_int32, C.c_int32,
                                      C.c_double, C.c_double, C.c_double]),
             "or_num_threads": (C.c_int, []),
@@ -373,18 +376,48 @@ def filter_update(params: dict, k: int, x, z) -> dict:
     return dict(lw=lw, w=w, est=est, ess=ess.value, anc=anc, x_next=xn, degenerate=bool(deg))
 
 
-def smc_run(src, tgt, params: dict, fp64_mode=False) -> dict:
-    s, t = _vol(src), _vol(tgt)
+def smc_run(src, tgt, params: dict, fp64_mode=False, frames=None) -> dict:
+    """Whole registration; ``frames`` optionally lists further (src, tgt)
+    frame pairs scored together with the first (multi-frame score)."""
+    pairs = [(_vol(src), _vol(tgt))] + [(_vol(a), _vol(b)) for a, b in (frames or [])]
     pr = make_params(params, fp64_mode)
     n, K = pr.n_particles, pr.n_iters
     est = np.zeros(6)
     ts, te, tx = np.zeros(K + 1), np.zeros(K), np.zeros((K, 6))
     x, lw = np.zeros((n, 6)), np.zeros(n)
     anc = np.zeros(n, np.int32)
-    sv, tv = s.c(), t.c()
-    deg = lib().or_smc_run(C.byref(sv), C.byref(tv), C.byref(pr), est, ts, te, tx, x, lw, anc)
+    svs = (_Vol * len(pairs))(*[a.c() for a, _ in pairs])
+    tvs = (_Vol * len(pairs))(*[b.c() for _, b in pairs])
+    deg = lib().or_smc_run_frames(svs, tvs, len(pairs), C.byref(pr), est, ts, te, tx, x, lw, anc)
     return dict(est=est, trace_score=ts, trace_ess=te, trace_est=tx, states=x, logw=lw, ancestors=anc,
                 degenerate=bool(deg))
+
+
+class Frames:
+    """Several (src, tgt) frame pairs scored together under one transform."""
+
+    def __init__(self, pairs):
+        self.vols = [(_vol(a), _vol(b)) for a, b in pairs]
+        self.pbs = (_Problem * len(self.vols))()
+        self._keep = []
+        for f, (a, b) in enumerate(self.vols):
+            av, bv = a.c(), b.c()
+            self._keep += [av, bv]
+            lib().or_problem_init(C.byref(self.pbs[f]), C.byref(av), C.byref(bv))
+
+    def sums(self, params: dict, x) -> np.ndarray:
+        pr = make_params(params)
+        x = np.ascontiguousarray(x, float).reshape(-1, 6)
+        out = np.zeros((len(x), 6), np.int64)
+        for i in range(len(x)):
+            lib().or_frame_sums(self.pbs, len(self.vols), C.byref(pr), x[i], out[i])
+        return out
+
+    def score(self, params: dict, x) -> np.ndarray:
+        pr = make_params(params)
+        x = np.ascontiguousarray(x, float).reshape(-1, 6)
+        return np.array([lib().or_score_particle_frames(self.pbs, len(self.vols), C.byref(pr), x[i])
+                         for i in range(len(x))])
 
 
 def warp_apply(src, M, trilinear, out_shape_xyz, out_spacing=(1.0, 1.0, 1.0)) -> np.ndarray:

@@ -621,6 +621,52 @@ double or_score_particle(const or_problem *pb, const or_params *pr, const double
     return -or_msd_from_moments(m, pb->mu_s, pb->sd_s, pb->mu_t, pb->sd_t);
 }
 
+/* ---- several frame pairs under one transform (multi-frame score): the
+ * integer sums of every frame pair are added before the score is formed, so
+ * Dice is 2 sum(a) / (sum(b) + sum(|T|)) and NCC is Eq. 2 over the union of
+ * the overlaps.  Recipe mode; Dice and NCC (the normalised SSD keeps a
+ * per-volume normalisation and is not pooled). */
+
+/* Pooled sums of particle p over nf frame pairs: masks (n, a, c, b_overlap,
+ * 0, 0), images the six moments. */
+void or_frame_sums(const or_problem *pbs, uint32_t nf, const or_params *pr, const double p[6], int64_t out[6])
+{
+    for (int q = 0; q < 6; ++q) out[q] = 0;
+    for (uint32_t f = 0; f < nf; ++f) {
+        float w[12];
+        if (pr->score == OR_SCORE_DICE) {
+            uint64_t cnt[4];
+            or_recipe_words(p, &pbs[f].src, &pbs[f].tgt, 1, w);
+            or_mask_counts(&pbs[f].src, &pbs[f].tgt, w, cnt);
+            for (int q = 0; q < 4; ++q) out[q] += (int64_t)cnt[q];
+        } else {
+            int64_t mi[6];
+            or_recipe_words(p, &pbs[f].src, &pbs[f].tgt, !pr->trilinear, w);
+            or_image_moments(&pbs[f].src, &pbs[f].tgt, w, pr->trilinear, mi);
+            for (int q = 0; q < 6; ++q) out[q] += mi[q];
+        }
+    }
+}
+
+double or_score_particle_frames(const or_problem *pbs, uint32_t nf, const or_params *pr, const double p[6])
+{
+    if (nf == 1) return or_score_particle(pbs, pr, p);
+    if (pr->score == OR_SCORE_SSD || pr->fp64_mode) return NAN;
+    int64_t m[6];
+    or_frame_sums(pbs, nf, pr, p, m);
+    if (pr->score == OR_SCORE_DICE) {
+        uint64_t t_on = 0;
+        for (uint32_t f = 0; f < nf; ++f) t_on += pbs[f].t_on;
+        return or_dice((uint64_t)m[1], (uint64_t)m[2], t_on);
+    }
+    uint64_t t_fov = 0;
+    for (uint32_t f = 0; f < nf; ++f) t_fov += pbs[f].t_fov;
+    if ((uint64_t)m[0] < (uint64_t)ceil(pr->min_overlap_frac * (double)t_fov)) return -INFINITY;
+    double md[6];
+    or_moments_to_double(m, md);
+    return or_ncc_from_moments(md);
+}
+
 /* ------------------------------------------------------------------ filter */
 
 /* Measurement update: log-likelihood of score z, a Gaussian in the deficit
@@ -863,16 +909,17 @@ int or_filter_update(const or_params *pr, uint32_t k, const double *x, const dou
     return degen;
 }
 
-/* Whole registration.  trace_score has K + 1 entries: the score of the
- * estimate before iteration 1 (x0) and after each iteration; trace_ess and
- * trace_est (6 per iteration) have K.  x_out receives the final particle
- * set, lw_out its log-weights, anc_out the last ancestors (or -1). */
-int or_smc_run(const or_vol *src, const or_vol *tgt, const or_params *pr, double est_out[6],
-               double *trace_score, double *trace_ess, double *trace_est, double *x_out, double *lw_out,
-               int32_t *anc_out)
+/* Whole registration over nf frame pairs scored together (nf = 1: one pair).
+ * trace_score has K + 1 entries: the score of the estimate before iteration 1
+ * (x0) and after each iteration; trace_ess and trace_est (6 per iteration)
+ * have K.  x_out receives the final particle set, lw_out its log-weights,
+ * anc_out the last ancestors (or -1). */
+int or_smc_run_frames(const or_vol *srcs, const or_vol *tgts, uint32_t nf, const or_params *pr,
+                      double est_out[6], double *trace_score, double *trace_ess, double *trace_est, double *x_out,
+                      double *lw_out, int32_t *anc_out)
 {
-    or_problem pb;
-    or_problem_init(&pb, src, tgt);
+    or_problem *pbs = (or_problem *)malloc(sizeof(or_problem) * nf);
+    for (uint32_t f = 0; f < nf; ++f) or_problem_init(&pbs[f], &srcs[f], &tgts[f]);
     uint32_t n = pr->n_particles;
     double *x = (double *)malloc(sizeof(double) * 6 * n);
     double *xn = (double *)malloc(sizeof(double) * 6 * n);
@@ -888,8 +935,9 @@ int or_smc_run(const or_vol *src, const or_vol *tgt, const or_params *pr, double
     if (pr->has_proposal) init_proposal(pr, x, lq);
     else or_init_particles(pr, x);
     for (uint32_t k = 1; k <= pr->n_iters; ++k) {
-        or_score_particles(&pb, pr, n, x, z);
-        if (trace_score) trace_score[k - 1] = or_score_particle(&pb, pr, est);
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t i = 0; i < (int64_t)n; ++i) z[i] = or_score_particle_frames(pbs, nf, pr, x + 6 * i);
+        if (trace_score) trace_score[k - 1] = or_score_particle_frames(pbs, nf, pr, est);
         double ess;
         degen_any |= or_filter_update(pr, k, x, z, lq, lw, w, est, &ess, anc, xn);
         if (trace_ess) trace_ess[k - 1] = ess;
@@ -898,13 +946,20 @@ int or_smc_run(const or_vol *src, const or_vol *tgt, const or_params *pr, double
             double *t = x; x = xn; xn = t;
         }
     }
-    if (trace_score) trace_score[pr->n_iters] = or_score_particle(&pb, pr, est);
+    if (trace_score) trace_score[pr->n_iters] = or_score_particle_frames(pbs, nf, pr, est);
     memcpy(est_out, est, sizeof est);
     if (x_out) memcpy(x_out, x, sizeof(double) * 6 * n);
     if (lw_out) memcpy(lw_out, lw, sizeof(double) * n);
     if (anc_out) memcpy(anc_out, anc, sizeof(int32_t) * n);
-    free(x); free(xn); free(z); free(lw); free(w); free(anc); free(lq);
+    free(x); free(xn); free(z); free(lw); free(w); free(anc); free(lq); free(pbs);
     return degen_any;
+}
+
+int or_smc_run(const or_vol *src, const or_vol *tgt, const or_params *pr, double est_out[6],
+               double *trace_score, double *trace_ess, double *trace_est, double *x_out, double *lw_out,
+               int32_t *anc_out)
+{
+    return or_smc_run_frames(src, tgt, 1, pr, est_out, trace_score, trace_ess, trace_est, x_out, lw_out, anc_out);
 }
 
 /* ------------------------------------------------------------------ warp apply */
