@@ -153,6 +153,23 @@ smc_status smc_set_particles(smc_ctx *ctx, const double *states_n6, uint32_t k_d
 smc_status smc_get_state(smc_ctx *ctx, void *buf, size_t *len);
 smc_status smc_set_state(smc_ctx *ctx, const void *buf, size_t len);
 
+/* Multi-frame score (Related Work: rigid registration with the ED and ES
+ * frames together, or all frames of the cycle): every evaluation of this
+ * context -- the filter's particles and estimate, smc_evaluate,
+ * smc_exhaustive -- scores each particle on its own source / target pair and
+ * on n_extra further frame pairs under the same transform, adding the
+ * integer sums of all pairs before the score is formed (Dice from the pooled
+ * counts and the pooled |T|; NCC over the union of the overlaps, with the
+ * minimum overlap taken over all target FOVs).  src_frames[q] / tgt_frames[q]
+ * (host arrays of n_extra volume descriptors; the volumes are device memory
+ * owned by the caller and must outlive the context) must match the first
+ * pair's shapes and spacings and carry FOV masks exactly where it does.
+ * n_extra = 0 removes the frames.  SMC_EINVAL for SSD (its normalisation is
+ * per volume) or mismatched frames, SMC_ESTATE after the first iteration
+ * (smc_reset rewinds) or on a pair owned by a batch.  Syncs once per frame. */
+smc_status smc_set_frames(smc_ctx *ctx, uint32_t n_extra, const smc_volume *src_frames,
+                          const smc_volume *tgt_frames);
+
 /* Launch tuning of the warp-and-score kernel; results do not depend on it.
  * layout: trilinear source layout, 0 raw bytes (eight gathers per sample),
  * 1 x-pairs (uint16, four), 2 2x2 quads (uint32, two), 3 2x2x2 octets

@@ -30,7 +30,7 @@ EXPORTS = ("smc_init", "smc_reset", "smc_step", "smc_estimate", "smc_get_particl
            "smc_set_tuning", "smc_get_tuning", "smc_batch_init", "smc_batch_set_seeds", "smc_batch_run",
            "smc_batch_pair", "smc_batch_destroy", "smc_cnn_create", "smc_cnn_set_params", "smc_cnn_get_params",
            "smc_cnn_input", "smc_cnn_read_input", "smc_cnn_forward", "smc_cnn_backward", "smc_cnn_step", "smc_cnn_destroy",
-           "smc_set_proposal", "smc_exhaustive", "smc_autotune", "smc_batch_autotune")
+           "smc_set_proposal", "smc_exhaustive", "smc_autotune", "smc_batch_autotune", "smc_set_frames")
 
 
 class SmcError(RuntimeError):
@@ -80,6 +80,7 @@ def lib():
             "smc_profile": [vp, i32],
             "smc_profile_read": [vp, vp, vp, vp, vp],
             "smc_set_tuning": [vp, i32, i32, i32],
+            "smc_set_frames": [vp, u32, vp, vp],
             "smc_get_tuning": [vp, vp, vp, vp],
             "smc_batch_init": [P(vp), u32, vp, vp, vp, vp],
             "smc_batch_set_seeds": [vp, vp],
@@ -283,6 +284,16 @@ def smc_set_tuning(ctx, layout=None, particles_per_group=None, tile_depth=None):
     _check(lib().smc_set_tuning(ctx, lay, pt, td))
 
 
+def smc_set_frames(ctx, src_frames, tgt_frames):
+    """Further frame pairs (lists of SmcVolume) scored with the first."""
+    n = len(src_frames)
+    if n != len(tgt_frames):
+        raise ValueError("src_frames and tgt_frames differ in length")
+    srcs = (SmcVolume * max(n, 1))(*src_frames)
+    tgts = (SmcVolume * max(n, 1))(*tgt_frames)
+    _check(lib().smc_set_frames(ctx, n, C.cast(srcs, C.c_void_p), C.cast(tgts, C.c_void_p)))
+
+
 def smc_get_tuning(ctx) -> dict:
     lay, pt, td = C.c_int32(), C.c_int32(), C.c_int32()
     _check(lib().smc_get_tuning(ctx, C.cast(C.byref(lay), C.c_void_p), C.cast(C.byref(pt), C.c_void_p),
@@ -328,6 +339,14 @@ class Registration:
 
     def evaluate(self, states):
         return smc_evaluate(self.ctx, states)
+
+    def set_frames(self, frames, spacing=(1.0, 1.0, 1.0), tgt_spacing=None):
+        """Score on further frame pairs too: ``frames`` is a list of dicts with
+        device tensors src, tgt and optional src_fov, tgt_fov."""
+        ts = spacing if tgt_spacing is None else tgt_spacing
+        self._frames = [(q["src"], q["tgt"], q.get("src_fov"), q.get("tgt_fov")) for q in frames]
+        smc_set_frames(self.ctx, [volume(q["src"], spacing, q.get("src_fov")) for q in frames],
+                       [volume(q["tgt"], ts, q.get("tgt_fov")) for q in frames])
 
     def set_particles(self, states, k_done):
         smc_set_particles(self.ctx, states, k_done)

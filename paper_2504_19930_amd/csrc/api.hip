@@ -125,6 +125,12 @@ struct smc_ctx {
     bool has_sentinel[kLayouts] = {};
     FilterState f{};
     uint32_t k_done = 0;
+    // target |T| and FOV voxel count of this pair (the score constants pool them over frames)
+    uint64_t tgt_on = 0, tgt_count = 0;
+    // multi-frame score: further frame pairs, each prepared by a context of its
+    // own; their score launches write into this context's words and sums
+    std::vector<smc_ctx *> frames;
+    bool in_batch = false;
     smc_status sticky = SMC_OK;
     std::string sticky_msg;
     // smc_evaluate workspace
@@ -301,13 +307,36 @@ smc_status ensure_eval(smc_ctx *c, uint32_t n) {
     return SMC_OK;
 }
 
+// Score particles p0 .. p0 + np - 1 of `words` into `sums`: the context's own
+// frame pair, then every further frame pair of a multi-frame score (integer
+// sums, so the pooled result does not depend on the order).
+hipError_t launch_score_frames(smc_ctx *c, const float *words, unsigned long long *sums, uint32_t p0, uint32_t np,
+                               bool filter) {
+    hipError_t e = launch_score(c->score_launch(words, sums, p0, np, filter), c->stream);
+    for (size_t q = 0; q < c->frames.size() && e == hipSuccess; ++q)
+        e = launch_score(c->frames[q]->score_launch(words, sums, p0, np, filter), c->stream);
+    return e;
+}
+
+// Score constants of the pooled frames: |T| and the minimum overlap count
+// over all target frames.
+void pool_frame_constants(smc_ctx *c) {
+    uint64_t on = c->tgt_on, count = c->tgt_count;
+    for (smc_ctx *fr : c->frames) {
+        on += fr->tgt_on;
+        count += fr->tgt_count;
+    }
+    c->f.sc.t_on = on;
+    c->f.sc.min_n = (uint64_t)ceil(c->p.min_overlap_frac * (double)count);
+}
+
 // Score a device particle set with the context's kernel; sums into s_eval.
 smc_status evaluate_device(smc_ctx *c, const double *x_dev, uint32_t n) {
     smc_status st = ensure_eval(c, n);
     if (st != SMC_OK) return st;
     HIP_TRY(launch_words(x_dev, n, c->f.geom, c->f.nearest, c->w_eval, c->stream));
     HIP_TRY(launch_fill_u64(c->s_eval, 6ull * n, c->stream));
-    HIP_TRY(launch_score(c->score_launch(c->w_eval, c->s_eval, 0, n), c->stream));
+    HIP_TRY(launch_score_frames(c, c->w_eval, c->s_eval, 0, n, false));
     return SMC_OK;
 }
 
@@ -404,6 +433,8 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
         return bail(fail(SMC_EDEVICE, "reading volume statistics failed: %s", hipGetErrorString(hipGetLastError())));
     const Stats ts = stats_from_sums(hs), ss = stats_from_sums(hs + 4);
     if (ts.count == 0) return bail(fail(SMC_EINVAL, "the target FOV is empty"));
+    c->tgt_on = ts.on;
+    c->tgt_count = ts.count;
 
     FilterState &f = c->f;
     f.n = n;
@@ -463,14 +494,13 @@ smc_status smc_step(smc_ctx *c, uint32_t n_iters) {
     if ((uint64_t)c->k_done + n_iters > c->f.n_iters)
         return fail(SMC_ESTATE, "%u iterations requested, %u of %u already run", n_iters, c->k_done, c->f.n_iters);
     if ((st = set_device(c)) != SMC_OK) return c->mark(st);
-    const ScoreLaunch all = c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true);
-    const ScoreLaunch ghost = c->score_launch(c->f.words, c->f.sums, c->f.n, 1, true);
     for (uint32_t it = 0; it < n_iters; ++it) {
         const uint32_t k = c->k_done + 1;
-        hipError_t e = timed(c, c->ev_score, [&] { return launch_score(all, c->stream); });
+        hipError_t e = timed(c, c->ev_score,
+                             [&] { return launch_score_frames(c, c->f.words, c->f.sums, 0, c->f.n + 1, true); });
         if (e == hipSuccess) e = timed(c, c->ev_filter, [&] { return launch_filter(c->f, k, c->stream); });
         if (e == hipSuccess && k == c->f.n_iters) {
-            e = launch_score(ghost, c->stream);
+            e = launch_score_frames(c, c->f.words, c->f.sums, c->f.n, 1, true);
             if (e == hipSuccess) e = launch_ghost_final(c->f, c->stream);
         }
         if (e != hipSuccess) return c->mark(fail(SMC_EDEVICE, "iteration %u launch failed: %s", k, hipGetErrorString(e)));
@@ -525,7 +555,7 @@ smc_status smc_exhaustive(smc_ctx *c, const double lo[6], const double step[6], 
         HIP_TRY(launch_grid_words(lo, step, count, first, n, c->f.geom, c->f.nearest, c->x_eval, c->w_eval,
                                   c->stream));
         HIP_TRY(launch_fill_u64(c->s_eval, 6ull * n, c->stream));
-        HIP_TRY(launch_score(c->score_launch(c->w_eval, c->s_eval, 0, n, true), c->stream));
+        HIP_TRY(launch_score_frames(c, c->w_eval, c->s_eval, 0, n, true));
         HIP_TRY(launch_chunk_best(c->s_eval, n, first, c->f.sc, dscores ? dscores + first : nullptr, dz + q, di + q,
                                   c->stream));
     }
@@ -692,6 +722,53 @@ smc_status smc_set_state(smc_ctx *c, const void *buf, size_t len) {
     return SMC_OK;
 }
 
+smc_status smc_set_frames(smc_ctx *c, uint32_t n_extra, const smc_volume *src_frames,
+                          const smc_volume *tgt_frames) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (n_extra > 4096) return fail(SMC_EINVAL, "n_extra must be at most 4096");
+    if (n_extra > 0 && (!src_frames || !tgt_frames)) return fail(SMC_EINVAL, "src_frames and tgt_frames must not be NULL");
+    if (c->in_batch) return fail(SMC_ESTATE, "frames cannot be added to a pair owned by a batch");
+    if (c->k_done != 0) return fail(SMC_ESTATE, "frames must be set before the first iteration (smc_reset rewinds)");
+    if (n_extra > 0 && c->p.score == SMC_SCORE_SSD)
+        return fail(SMC_EINVAL, "the normalised SSD keeps per-volume statistics and is not pooled over frames");
+    smc_status st;
+    for (uint32_t q = 0; q < n_extra; ++q) {
+        const smc_volume *s = &src_frames[q], *t = &tgt_frames[q];
+        if ((st = check_volume(s, "src frame")) != SMC_OK || (st = check_volume(t, "tgt frame")) != SMC_OK) return st;
+        if (s->nx != c->sn[0] || s->ny != c->sn[1] || s->nz != c->sn[2] || t->nx != c->tn[0] || t->ny != c->tn[1] ||
+            t->nz != c->tn[2])
+            return fail(SMC_EINVAL, "frame %u: shapes differ from the context's source / target", q + 1);
+        if (s->sx != c->f.geom.ss[0] || s->sy != c->f.geom.ss[1] || s->sz != c->f.geom.ss[2] ||
+            t->sx != c->f.geom.ts[0] || t->sy != c->f.geom.ts[1] || t->sz != c->f.geom.ts[2])
+            return fail(SMC_EINVAL, "frame %u: spacings differ from the context's source / target", q + 1);
+        if ((s->fov == nullptr) != (c->src_fov == nullptr) || (t->fov == nullptr) != (c->tgt_fov == nullptr))
+            return fail(SMC_EINVAL, "frame %u: FOV masks must be given for the same volumes as the first pair", q + 1);
+    }
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    for (smc_ctx *fr : c->frames) smc_destroy(fr);
+    c->frames.clear();
+    // each further pair is prepared by a context of its own (one particle,
+    // one iteration: only its prepared volumes and launch settings are used)
+    smc_params fp = c->p;
+    fp.n_particles = 1;
+    fp.n_iters = 1;
+    for (uint32_t q = 0; q < n_extra; ++q) {
+        smc_ctx *fr = nullptr;
+        if ((st = smc_init(&fr, &src_frames[q], &tgt_frames[q], &fp, c->stream)) != SMC_OK) {
+            const std::string msg = g_err;
+            for (smc_ctx *g : c->frames) smc_destroy(g);
+            c->frames.clear();
+            pool_frame_constants(c);
+            return fail(st, "frame %u: %s", q + 1, msg.c_str());
+        }
+        c->frames.push_back(fr);
+        if ((st = smc_set_tuning(fr, c->layout, c->pt, c->zchunk)) != SMC_OK) return c->mark(st);
+    }
+    pool_frame_constants(c);
+    return SMC_OK;
+}
+
 smc_status smc_set_tuning(smc_ctx *c, int32_t layout, int32_t pt, int32_t tile_depth) {
     if (!c) return fail(SMC_EINVAL, "ctx is NULL");
     if (tile_depth == 0 || tile_depth > 256) return fail(SMC_EINVAL, "tile_depth must be in 1..256");
@@ -707,6 +784,8 @@ smc_status smc_set_tuning(smc_ctx *c, int32_t layout, int32_t pt, int32_t tile_d
         if ((st = prepare_layout(c, layout)) != SMC_OK) return c->mark(st);
         c->layout = layout;
     }
+    for (smc_ctx *fr : c->frames)
+        if ((st = smc_set_tuning(fr, layout, pt, tile_depth)) != SMC_OK) return c->mark(st);
     if (pt >= 0) c->pt = pt;
     if (tile_depth > 0) c->zchunk = tile_depth;
     return SMC_OK;
@@ -848,6 +927,7 @@ void smc_destroy(smc_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    for (smc_ctx *fr : c->frames) smc_destroy(fr);
     for (void *ptr : c->allocs) (void)hipFree(ptr);
     for (auto *log : {&c->ev_score, &c->ev_filter})
         for (auto &pr : *log) {
@@ -1067,6 +1147,7 @@ smc_status smc_batch_init(smc_batch **out, uint32_t n_pairs, const smc_volume *s
             std::string msg = g_err;
             return bail(fail(st, "pair %u: %s", i, msg.c_str()));
         }
+        c->in_batch = true;
         b->pairs.push_back(c);
         b->states.push_back(c->f);
         b->kmax_all = std::max(b->kmax_all, c->f.n_iters);

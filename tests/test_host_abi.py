@@ -81,6 +81,7 @@ def test_null_arguments(smc):
     assert L.smc_step(None, 1) == smc.SMC_EINVAL
     assert L.smc_estimate(None, None, None, None, None) == smc.SMC_EINVAL
     assert L.smc_get_particles(None, None, None, None) == smc.SMC_EINVAL
+    assert L.smc_set_frames(None, 0, None, None) == smc.SMC_EINVAL
     L.smc_destroy(None)
     M = np.eye(3, 4)
     src = _vol(smc)
