@@ -91,7 +91,8 @@ def cpu_baseline(pair, prm, target_s: float):
     s = oracle.Volume(pair["src"], fov=pair["src_fov"])
     t = oracle.Volume(pair["tgt"])
     pb = oracle.Problem(s, t)
-    x = oracle.init_particles(prm)
+    # a larger draw from the same prior, so the sample is not capped at N
+    x = oracle.init_particles(dict(prm, n_particles=16 * prm["n_particles"]))
     V = pair["tgt"].size
     threads = oracle.num_threads()
     n = max(1, threads)
@@ -115,7 +116,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--score", default="ncc", choices=["ncc", "ssd"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-time-to-dice", action="store_true")
     ap.add_argument("--ttd-pairs", type=int, default=2)
     ap.add_argument("--tuning", default=DEFAULT_TUNING,
