@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "smc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-SCORES = {"dice": 0, "ncc": 1, "ssd": 2}
+SCORES = {"dice": 0, "ncc": 1, "ssd": 2, "mi": 3}
 
 
 def build(force: bool = True) -> str:
@@ -104,6 +104,8 @@ def lib():
             "or_warp_apply": (None, [P(_Vol), d, C.c_int, u8, C.c_int32, C.c_int32, C.c_int32,
                                      C.c_double, C.c_double, C.c_double]),
             "or_num_threads": (C.c_int, []),
+            "or_joint_histogram": (None, [P(_Vol), P(_Vol), f32, u64]),
+            "or_mi_score": (C.c_double, [u64]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -238,6 +240,19 @@ def image_moments_fp64(src, tgt, p, trilinear=True) -> np.ndarray:
     lib().or_image_moments_fp64(C.byref(s.c()), C.byref(t.c()), np.asarray(p, float),
                                 1 if trilinear else 0, out)
     return out
+
+
+def joint_histogram(src, tgt, words) -> np.ndarray:
+    """32 x 32 joint histogram (source bin, target bin) of the trilinear MI score."""
+    s, t = _vol(src), _vol(tgt)
+    sv, tv = s.c(), t.c()
+    h = np.zeros(32 * 32, np.uint64)
+    lib().or_joint_histogram(C.byref(sv), C.byref(tv), np.ascontiguousarray(words, np.float32), h)
+    return h.reshape(32, 32)
+
+
+def mi_score(hist) -> float:
+    return lib().or_mi_score(np.ascontiguousarray(hist, np.uint64).reshape(-1))
 
 
 def dice(a, c, b) -> float:

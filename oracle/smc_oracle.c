@@ -45,6 +45,8 @@
 #include <omp.h>
 #endif
 
+#define OR_MI_BINS 32 /* joint-histogram bins per axis of the MI score */
+
 /* ------------------------------------------------------------------ Philox */
 
 /* Philox4x32-10: ten rounds of (two 32x32->64 multiplies, xor with the other
@@ -315,6 +317,51 @@ static inline float lerpf_r(float a, float b, float f) { return fmaf(f, b - a, a
  * 0 <= u_d <= n_d - 1 and all eight corners in the source FOV; corners
  * i0 = floor(u), i1 = min(i0 + 1, n - 1), f = u - i0, lerps along x, then y,
  * then z.  Nearest: as the mask rule, s_fx = 256 S[m]. */
+/* The sampled source value at target voxel (i, j, k) in fixed point,
+ * s_fx = floor(256 s + 0.5), and whether the sample is in the overlap:
+ * trilinear inside iff 0 <= u <= n - 1 on every axis and the eight corners
+ * in the source FOV; nearest (the words carry the +0.5 shift) inside iff
+ * 0 <= u < n and the voxel in the source FOV. */
+static int sample_fx(const or_vol *src, const float w[12], int trilinear, int i, int j, int k, uint64_t *sfx)
+{
+    float u[3];
+    for (int d = 0; d < 3; ++d) u[d] = recipe_u(w, d, (float)i, (float)j, (float)k);
+    if (trilinear) {
+        if (!(u[0] >= 0.0f && u[0] <= (float)(src->nx - 1) && u[1] >= 0.0f &&
+              u[1] <= (float)(src->ny - 1) && u[2] >= 0.0f && u[2] <= (float)(src->nz - 1)))
+            return 0;
+        int i0 = (int)floorf(u[0]), j0 = (int)floorf(u[1]), k0 = (int)floorf(u[2]);
+        float fx = u[0] - (float)i0, fy = u[1] - (float)j0, fz = u[2] - (float)k0;
+        int i1 = i0 + 1 < src->nx ? i0 + 1 : src->nx - 1;
+        int j1 = j0 + 1 < src->ny ? j0 + 1 : src->ny - 1;
+        int k1 = k0 + 1 < src->nz ? k0 + 1 : src->nz - 1;
+        size_t c000 = vidx(src, i0, j0, k0), c100 = vidx(src, i1, j0, k0);
+        size_t c010 = vidx(src, i0, j1, k0), c110 = vidx(src, i1, j1, k0);
+        size_t c001 = vidx(src, i0, j0, k1), c101 = vidx(src, i1, j0, k1);
+        size_t c011 = vidx(src, i0, j1, k1), c111 = vidx(src, i1, j1, k1);
+        if (src->fov && !(src->fov[c000] && src->fov[c100] && src->fov[c010] && src->fov[c110] &&
+                          src->fov[c001] && src->fov[c101] && src->fov[c011] && src->fov[c111]))
+            return 0;
+        const uint8_t *S = src->data;
+        float x00 = lerpf_r((float)S[c000], (float)S[c100], fx);
+        float x10 = lerpf_r((float)S[c010], (float)S[c110], fx);
+        float x01 = lerpf_r((float)S[c001], (float)S[c101], fx);
+        float x11 = lerpf_r((float)S[c011], (float)S[c111], fx);
+        float y0 = lerpf_r(x00, x10, fy);
+        float y1 = lerpf_r(x01, x11, fy);
+        float s = lerpf_r(y0, y1, fz);
+        *sfx = (uint64_t)floorf(s * 256.0f + 0.5f);
+        return 1;
+    }
+    if (!(u[0] >= 0.0f && u[0] < (float)src->nx && u[1] >= 0.0f && u[1] < (float)src->ny && u[2] >= 0.0f &&
+          u[2] < (float)src->nz))
+        return 0;
+    size_t si = vidx(src, (int)floorf(u[0]), (int)floorf(u[1]), (int)floorf(u[2]));
+    if (src->fov && src->fov[si] == 0) return 0;
+    *sfx = (uint64_t)src->data[si] * 256u;
+    return 1;
+}
+
 void or_image_moments(const or_vol *src, const or_vol *tgt, const float w[12], int trilinear,
                       int64_t out[6])
 {
@@ -324,43 +371,8 @@ void or_image_moments(const or_vol *src, const or_vol *tgt, const float w[12], i
             for (int i = 0; i < tgt->nx; ++i) {
                 size_t ti = vidx(tgt, i, j, k);
                 if (tgt->fov && tgt->fov[ti] == 0) continue;
-                float u[3];
-                for (int d = 0; d < 3; ++d) u[d] = recipe_u(w, d, (float)i, (float)j, (float)k);
                 uint64_t sfx;
-                if (trilinear) {
-                    if (!(u[0] >= 0.0f && u[0] <= (float)(src->nx - 1) && u[1] >= 0.0f &&
-                          u[1] <= (float)(src->ny - 1) && u[2] >= 0.0f && u[2] <= (float)(src->nz - 1)))
-                        continue;
-                    int i0 = (int)floorf(u[0]), j0 = (int)floorf(u[1]), k0 = (int)floorf(u[2]);
-                    float fx = u[0] - (float)i0, fy = u[1] - (float)j0, fz = u[2] - (float)k0;
-                    int i1 = i0 + 1 < src->nx ? i0 + 1 : src->nx - 1;
-                    int j1 = j0 + 1 < src->ny ? j0 + 1 : src->ny - 1;
-                    int k1 = k0 + 1 < src->nz ? k0 + 1 : src->nz - 1;
-                    size_t c000 = vidx(src, i0, j0, k0), c100 = vidx(src, i1, j0, k0);
-                    size_t c010 = vidx(src, i0, j1, k0), c110 = vidx(src, i1, j1, k0);
-                    size_t c001 = vidx(src, i0, j0, k1), c101 = vidx(src, i1, j0, k1);
-                    size_t c011 = vidx(src, i0, j1, k1), c111 = vidx(src, i1, j1, k1);
-                    if (src->fov && !(src->fov[c000] && src->fov[c100] && src->fov[c010] && src->fov[c110] &&
-                                      src->fov[c001] && src->fov[c101] && src->fov[c011] && src->fov[c111]))
-                        continue;
-                    const uint8_t *S = src->data;
-                    float x00 = lerpf_r((float)S[c000], (float)S[c100], fx);
-                    float x10 = lerpf_r((float)S[c010], (float)S[c110], fx);
-                    float x01 = lerpf_r((float)S[c001], (float)S[c101], fx);
-                    float x11 = lerpf_r((float)S[c011], (float)S[c111], fx);
-                    float y0 = lerpf_r(x00, x10, fy);
-                    float y1 = lerpf_r(x01, x11, fy);
-                    float s = lerpf_r(y0, y1, fz);
-                    sfx = (uint64_t)floorf(s * 256.0f + 0.5f);
-                } else {
-                    /* nearest: the words carry the +0.5 shift */
-                    if (!(u[0] >= 0.0f && u[0] < (float)src->nx && u[1] >= 0.0f && u[1] < (float)src->ny &&
-                          u[2] >= 0.0f && u[2] < (float)src->nz))
-                        continue;
-                    size_t si = vidx(src, (int)floorf(u[0]), (int)floorf(u[1]), (int)floorf(u[2]));
-                    if (src->fov && src->fov[si] == 0) continue;
-                    sfx = (uint64_t)src->data[si] * 256u;
-                }
+                if (!sample_fx(src, w, trilinear, i, j, k, &sfx)) continue;
                 uint64_t t = tgt->data[ti];
                 n += 1;
                 ss += sfx;
@@ -371,6 +383,50 @@ void or_image_moments(const or_vol *src, const or_vol *tgt, const float w[12], i
             }
     out[0] = (int64_t)n; out[1] = (int64_t)ss; out[2] = (int64_t)st;
     out[3] = (int64_t)sss; out[4] = (int64_t)stt; out[5] = (int64_t)sst;
+}
+
+/* ---- mutual information (Related Work: the MI metric of landmark-free
+ * echo registration).  Joint histogram of (source bin, target bin) over the
+ * same overlap as the moments, OR_MI_BINS per axis: source bin s_fx >> 11
+ * (s_fx <= 65280), target bin t >> 3.  Score: the symmetric uncertainty
+ * 2 I(S;T) / (H(S) + H(T)) from the histogram's joint and marginal
+ * frequencies, in [0, 1] and 1 for images equal up to a bijection of bins;
+ * 0 when both marginal entropies vanish. ---- */
+
+void or_joint_histogram(const or_vol *src, const or_vol *tgt, const float w[12], uint64_t *hist)
+{
+    memset(hist, 0, sizeof(uint64_t) * OR_MI_BINS * OR_MI_BINS);
+    for (int k = 0; k < tgt->nz; ++k)
+        for (int j = 0; j < tgt->ny; ++j)
+            for (int i = 0; i < tgt->nx; ++i) {
+                size_t ti = vidx(tgt, i, j, k);
+                if (tgt->fov && tgt->fov[ti] == 0) continue;
+                uint64_t sfx;
+                if (!sample_fx(src, w, 1, i, j, k, &sfx)) continue;
+                hist[(sfx >> 11) * OR_MI_BINS + (tgt->data[ti] >> 3)] += 1;
+            }
+}
+
+double or_mi_score(const uint64_t *hist)
+{
+    uint64_t n = 0, ms[OR_MI_BINS] = {0}, mt[OR_MI_BINS] = {0};
+    for (int a = 0; a < OR_MI_BINS; ++a)
+        for (int b = 0; b < OR_MI_BINS; ++b) {
+            uint64_t c = hist[a * OR_MI_BINS + b];
+            n += c;
+            ms[a] += c;
+            mt[b] += c;
+        }
+    if (n == 0) return 0.0;
+    double N = (double)n, hs = 0.0, ht = 0.0, hst = 0.0;
+    for (int a = 0; a < OR_MI_BINS; ++a) {
+        if (ms[a]) hs -= ((double)ms[a] / N) * log((double)ms[a] / N);
+        if (mt[a]) ht -= ((double)mt[a] / N) * log((double)mt[a] / N);
+    }
+    for (int q = 0; q < OR_MI_BINS * OR_MI_BINS; ++q)
+        if (hist[q]) hst -= ((double)hist[q] / N) * log((double)hist[q] / N);
+    if (hs + ht <= 0.0) return 0.0;
+    return 2.0 * (hs + ht - hst) / (hs + ht);
 }
 
 /* ---- FP64 mode: the same definitions with FP64 coordinates and values. ---- */
@@ -526,7 +582,7 @@ void or_moments_to_double(const int64_t mi[6], double m[6])
 
 /* ------------------------------------------------------------------ problem */
 
-enum { OR_SCORE_DICE = 0, OR_SCORE_NCC = 1, OR_SCORE_SSD = 2 };
+enum { OR_SCORE_DICE = 0, OR_SCORE_NCC = 1, OR_SCORE_SSD = 2, OR_SCORE_MI = 3 };
 
 typedef struct {
     uint32_t n_particles, n_iters;
@@ -592,6 +648,16 @@ static uint64_t min_overlap(const or_problem *pb, const or_params *pr)
 double or_score_particle(const or_problem *pb, const or_params *pr, const double p[6])
 {
     int nn = pr->score == OR_SCORE_DICE ? 1 : !pr->trilinear;
+    if (pr->score == OR_SCORE_MI) {
+        if (pr->fp64_mode || !pr->trilinear) return NAN;
+        float w[12];
+        uint64_t h[OR_MI_BINS * OR_MI_BINS], n = 0;
+        or_recipe_words(p, &pb->src, &pb->tgt, 0, w);
+        or_joint_histogram(&pb->src, &pb->tgt, w, h);
+        for (int q = 0; q < OR_MI_BINS * OR_MI_BINS; ++q) n += h[q];
+        if (n < min_overlap(pb, pr)) return -INFINITY;
+        return or_mi_score(h);
+    }
     if (pr->score == OR_SCORE_DICE) {
         uint64_t cnt[4];
         if (pr->fp64_mode) {
@@ -652,6 +718,20 @@ double or_score_particle_frames(const or_problem *pbs, uint32_t nf, const or_par
 {
     if (nf == 1) return or_score_particle(pbs, pr, p);
     if (pr->score == OR_SCORE_SSD || pr->fp64_mode) return NAN;
+    if (pr->score == OR_SCORE_MI) {
+        uint64_t h[OR_MI_BINS * OR_MI_BINS], hf[OR_MI_BINS * OR_MI_BINS], n = 0, t_fov = 0;
+        memset(h, 0, sizeof h);
+        for (uint32_t f = 0; f < nf; ++f) {
+            float w[12];
+            or_recipe_words(p, &pbs[f].src, &pbs[f].tgt, 0, w);
+            or_joint_histogram(&pbs[f].src, &pbs[f].tgt, w, hf);
+            for (int q = 0; q < OR_MI_BINS * OR_MI_BINS; ++q) h[q] += hf[q];
+            t_fov += pbs[f].t_fov;
+        }
+        for (int q = 0; q < OR_MI_BINS * OR_MI_BINS; ++q) n += h[q];
+        if (n < (uint64_t)ceil(pr->min_overlap_frac * (double)t_fov)) return -INFINITY;
+        return or_mi_score(h);
+    }
     int64_t m[6];
     or_frame_sums(pbs, nf, pr, p, m);
     if (pr->score == OR_SCORE_DICE) {

@@ -11,7 +11,7 @@ from __future__ import annotations
 
 import math
 
-SIGMA_SCORE = {"dice": 0.01, "ncc": 0.02, "ssd": 0.1}
+SIGMA_SCORE = {"dice": 0.01, "ncc": 0.02, "ssd": 0.1, "mi": 0.02}
 
 
 def default_params(score: str, n_particles: int, n_iters: int, rot_limit_deg: float, trans_limit: float,
