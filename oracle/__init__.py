@@ -106,6 +106,7 @@ def lib():
             "or_num_threads": (C.c_int, []),
             "or_joint_histogram": (None, [P(_Vol), P(_Vol), f32, u64]),
             "or_mi_score": (C.c_double, [u64]),
+            "or_mi_log": (C.c_double, [C.c_double]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -249,6 +250,10 @@ def joint_histogram(src, tgt, words) -> np.ndarray:
     h = np.zeros(32 * 32, np.uint64)
     lib().or_joint_histogram(C.byref(sv), C.byref(tv), np.ascontiguousarray(words, np.float32), h)
     return h.reshape(32, 32)
+
+
+def mi_log(x: float) -> float:
+    return lib().or_mi_log(float(x))
 
 
 def mi_score(hist) -> float:

@@ -407,6 +407,26 @@ void or_joint_histogram(const or_vol *src, const or_vol *tgt, const float w[12],
             }
 }
 
+/* Natural logarithm for the MI score, the same on every platform: x = m 2^e
+ * with m in [sqrt(1/2), sqrt(2)), ln x = e ln 2 + 2 atanh(s), s = (m-1)/(m+1),
+ * |s| <= 0.172, by the series 2 (s + s^3/3 + ... + s^25/25) (error below
+ * 1e-20).  Written out so the score does not depend on the C library's log. */
+double or_mi_log(double x)
+{
+    int e;
+    double m = frexp(x, &e);
+    if (m < 0.7071067811865476) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    double s = (m - 1.0) / (m + 1.0), s2 = s * s, t = s, sum = s;
+    for (int k = 3; k <= 25; k += 2) {
+        t = t * s2;
+        sum = sum + t / (double)k;
+    }
+    return (double)e * 0.6931471805599453 + 2.0 * sum;
+}
+
 double or_mi_score(const uint64_t *hist)
 {
     uint64_t n = 0, ms[OR_MI_BINS] = {0}, mt[OR_MI_BINS] = {0};
@@ -420,11 +440,20 @@ double or_mi_score(const uint64_t *hist)
     if (n == 0) return 0.0;
     double N = (double)n, hs = 0.0, ht = 0.0, hst = 0.0;
     for (int a = 0; a < OR_MI_BINS; ++a) {
-        if (ms[a]) hs -= ((double)ms[a] / N) * log((double)ms[a] / N);
-        if (mt[a]) ht -= ((double)mt[a] / N) * log((double)mt[a] / N);
+        if (ms[a]) {
+            double f = (double)ms[a] / N;
+            hs = hs - f * or_mi_log(f);
+        }
+        if (mt[a]) {
+            double f = (double)mt[a] / N;
+            ht = ht - f * or_mi_log(f);
+        }
     }
     for (int q = 0; q < OR_MI_BINS * OR_MI_BINS; ++q)
-        if (hist[q]) hst -= ((double)hist[q] / N) * log((double)hist[q] / N);
+        if (hist[q]) {
+            double f = (double)hist[q] / N;
+            hst = hst - f * or_mi_log(f);
+        }
     if (hs + ht <= 0.0) return 0.0;
     return 2.0 * (hs + ht - hst) / (hs + ht);
 }

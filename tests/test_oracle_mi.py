@@ -74,3 +74,14 @@ def test_mi_registration_recovers_transform(orc):
     out = orc.smc_run(orc.Volume(pair["src"], fov=pair["src_fov"]), orc.Volume(pair["tgt"]), prm)
     err = np.abs(out["est"] - pair["gt"])
     assert np.degrees(err[:3]).max() < 2.0 and err[3:].max() < 1.0, (np.degrees(err[:3]), err[3:])
+
+
+def test_mi_log_matches_the_library_log(orc):
+    rng = np.random.default_rng(8)
+    xs = np.concatenate([rng.uniform(1e-9, 1.0, 20000), 10.0 ** rng.uniform(-300, 0, 2000),
+                         [1.0, 0.5, 2.0 ** -20, 1.0 / 3.0, 0.7071067811865476, 0.70710678118654746]])
+    for x in xs:
+        want = math.log(x)
+        got = orc.mi_log(x)
+        assert abs(got - want) <= 4 * np.spacing(abs(want)) + 1e-300, (x, got, want)
+    assert orc.mi_log(1.0) == 0.0
