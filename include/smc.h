@@ -46,8 +46,14 @@ typedef enum {
  * DICE: Eq. 4 on binary masks, over the whole target FOV, nearest neighbour.
  * NCC:  Eq. 2 (squared correlation, 0..1) over the overlap.
  * SSD:  mean squared difference of the mean-0 / std-1 normalised images
- *       (Implementation Details) over the overlap; the score is its negative. */
-typedef enum { SMC_SCORE_DICE = 0, SMC_SCORE_NCC = 1, SMC_SCORE_SSD = 2 } smc_score;
+ *       (Implementation Details) over the overlap; the score is its negative.
+ * MI:   mutual information (the metric Related Work lists beside NCC) over
+ *       the overlap, TRILINEAR only: a 32 x 32 joint histogram of exact
+ *       counts of (source bin, target bin), source bin = floor(256 s + 0.5)
+ *       >> 11, target bin = t >> 3, scored as the symmetric uncertainty
+ *       2 I(S;T) / (H(S) + H(T)) in [0, 1] (1 for images equal up to a
+ *       bijection of bins); overlaps below the minimum score -inf. */
+typedef enum { SMC_SCORE_DICE = 0, SMC_SCORE_NCC = 1, SMC_SCORE_SSD = 2, SMC_SCORE_MI = 3 } smc_score;
 
 /* Sampling of the source at non-grid positions (Implementation Details:
  * trilinear interpolation).  DICE requires NEAREST. */
@@ -130,7 +136,8 @@ smc_status smc_trace(smc_ctx *ctx, double *score_k1, double *ess_k, double *est_
  * (n x 6 int64): masks (n, a, c, b_ov, 0, 0); images (n, sum s_fx, sum t,
  * sum s_fx^2, sum t^2, sum s_fx t) with s_fx the interpolated source value in
  * units of 1/256.  Uses the context's buffers; leaves the filter state alone
- * but must not overlap smc_step on the same context.  Syncs. */
+ * but must not overlap smc_step on the same context.  Syncs.  SMC_EINVAL for
+ * the MI score, which has no moments (use smc_score_particles). */
 smc_status smc_evaluate(smc_ctx *ctx, const double *states_n6, uint32_t n, int64_t *moments_n6);
 
 /* Exhaustive search (the EX baseline of Baseline and Evaluation Metrics):
@@ -152,6 +159,11 @@ smc_status smc_set_particles(smc_ctx *ctx, const double *states_n6, uint32_t k_d
  * continues bit-identically.  Both sync. */
 smc_status smc_get_state(smc_ctx *ctx, void *buf, size_t *len);
 smc_status smc_set_state(smc_ctx *ctx, const void *buf, size_t len);
+
+/* Final scores z (as the filter sees them: Dice, NCC, -SSD or MI; -inf
+ * below the minimum overlap) of n host particle states (n x 6, FP64).
+ * Syncs.  SMC_EINVAL on NULL or non-finite input. */
+smc_status smc_score_particles(smc_ctx *ctx, const double *states_n6, uint32_t n, double *scores_n);
 
 /* Multi-frame score (Related Work: rigid registration with the ED and ES
  * frames together, or all frames of the cycle): every evaluation of this

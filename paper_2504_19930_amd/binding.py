@@ -19,7 +19,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsmc.so")
 
 SMC_OK, SMC_EINVAL, SMC_ENOMEM, SMC_EDEVICE, SMC_ESTATE = 0, -1, -2, -3, -4
-SCORES = {"dice": 0, "ncc": 1, "ssd": 2}
+SCORES = {"dice": 0, "ncc": 1, "ssd": 2, "mi": 3}
 INTERPS = {"nearest": 0, "trilinear": 1}
 ROTATIONS = {"box": 0, "wide": 1}
 
@@ -30,7 +30,8 @@ EXPORTS = ("smc_init", "smc_reset", "smc_step", "smc_estimate", "smc_get_particl
            "smc_set_tuning", "smc_get_tuning", "smc_batch_init", "smc_batch_set_seeds", "smc_batch_run",
            "smc_batch_pair", "smc_batch_destroy", "smc_cnn_create", "smc_cnn_set_params", "smc_cnn_get_params",
            "smc_cnn_input", "smc_cnn_read_input", "smc_cnn_forward", "smc_cnn_backward", "smc_cnn_step", "smc_cnn_destroy",
-           "smc_set_proposal", "smc_exhaustive", "smc_autotune", "smc_batch_autotune", "smc_set_frames")
+           "smc_set_proposal", "smc_exhaustive", "smc_autotune", "smc_batch_autotune", "smc_set_frames",
+           "smc_score_particles")
 
 
 class SmcError(RuntimeError):
@@ -81,6 +82,7 @@ def lib():
             "smc_profile_read": [vp, vp, vp, vp, vp],
             "smc_set_tuning": [vp, i32, i32, i32],
             "smc_set_frames": [vp, u32, vp, vp],
+            "smc_score_particles": [vp, vp, u32, vp],
             "smc_get_tuning": [vp, vp, vp, vp],
             "smc_batch_init": [P(vp), u32, vp, vp, vp, vp],
             "smc_batch_set_seeds": [vp, vp],
@@ -284,6 +286,13 @@ def smc_set_tuning(ctx, layout=None, particles_per_group=None, tile_depth=None):
     _check(lib().smc_set_tuning(ctx, lay, pt, td))
 
 
+def smc_score_particles(ctx, states) -> np.ndarray:
+    x = np.ascontiguousarray(states, dtype=np.float64).reshape(-1, 6)
+    out = np.zeros(len(x))
+    _check(lib().smc_score_particles(ctx, _ptr(x), len(x), _ptr(out)))
+    return out
+
+
 def smc_set_frames(ctx, src_frames, tgt_frames):
     """Further frame pairs (lists of SmcVolume) scored with the first."""
     n = len(src_frames)
@@ -339,6 +348,9 @@ class Registration:
 
     def evaluate(self, states):
         return smc_evaluate(self.ctx, states)
+
+    def scores(self, states):
+        return smc_score_particles(self.ctx, states)
 
     def set_frames(self, frames, spacing=(1.0, 1.0, 1.0), tgt_spacing=None):
         """Score on further frame pairs too: ``frames`` is a list of dicts with

@@ -69,11 +69,13 @@ smc_status check_params(const smc_params *p) {
     if (!p) return fail(SMC_EINVAL, "params is NULL");
     if (p->n_particles < 1 || p->n_particles > 65536) return fail(SMC_EINVAL, "n_particles must be in 1..65536");
     if (p->n_iters < 1 || p->n_iters > 100000) return fail(SMC_EINVAL, "n_iters must be in 1..100000");
-    if (p->score < SMC_SCORE_DICE || p->score > SMC_SCORE_SSD) return fail(SMC_EINVAL, "unknown score %d", p->score);
+    if (p->score < SMC_SCORE_DICE || p->score > SMC_SCORE_MI) return fail(SMC_EINVAL, "unknown score %d", p->score);
     if (p->interp != SMC_INTERP_NEAREST && p->interp != SMC_INTERP_TRILINEAR)
         return fail(SMC_EINVAL, "unknown interpolation %d", p->interp);
     if (p->rotation_mode != SMC_ROTATION_BOX && p->rotation_mode != SMC_ROTATION_WIDE)
         return fail(SMC_EINVAL, "unknown rotation_mode %d", p->rotation_mode);
+    if (p->score == SMC_SCORE_MI && p->interp != SMC_INTERP_TRILINEAR)
+        return fail(SMC_EINVAL, "the mutual-information score samples trilinearly");
     if (p->score == SMC_SCORE_DICE && p->interp != SMC_INTERP_NEAREST)
         return fail(SMC_EINVAL, "the Dice score works on binary masks with nearest-neighbour sampling");
     if (!finite6(p->x0) || !finite6(p->limit) || !finite6(p->sigma0))
@@ -138,6 +140,10 @@ struct smc_ctx {
     double *x_eval = nullptr;
     float *w_eval = nullptr;
     unsigned long long *s_eval = nullptr;
+    double *z_eval = nullptr;
+    // mutual information: joint histograms of the filter's particles (N + 1)
+    // and of the evaluation workspace (eval_cap), zero between evaluations
+    uint32_t *hist = nullptr, *hist_eval = nullptr;
     std::vector<void *> allocs;
     // kernel timing
     bool profiling = false;
@@ -303,6 +309,12 @@ smc_status ensure_eval(smc_ctx *c, uint32_t n) {
     if ((st = c->alloc(&c->x_eval, 6ull * n)) != SMC_OK) return st;
     if ((st = c->alloc(&c->w_eval, 12ull * n)) != SMC_OK) return st;
     if ((st = c->alloc(&c->s_eval, 6ull * n)) != SMC_OK) return st;
+    if ((st = c->alloc(&c->z_eval, n)) != SMC_OK) return st;
+    if (c->p.score == SMC_SCORE_MI) {
+        const uint64_t words = (uint64_t)kMiBins * kMiBins * n;
+        if ((st = c->alloc(&c->hist_eval, words)) != SMC_OK) return st;
+        HIP_TRY(launch_fill_u64((unsigned long long *)c->hist_eval, words / 2, c->stream));
+    }
     c->eval_cap = n;
     return SMC_OK;
 }
@@ -310,11 +322,19 @@ smc_status ensure_eval(smc_ctx *c, uint32_t n) {
 // Score particles p0 .. p0 + np - 1 of `words` into `sums`: the context's own
 // frame pair, then every further frame pair of a multi-frame score (integer
 // sums, so the pooled result does not depend on the order).
-hipError_t launch_score_frames(smc_ctx *c, const float *words, unsigned long long *sums, uint32_t p0, uint32_t np,
-                               bool filter) {
-    hipError_t e = launch_score(c->score_launch(words, sums, p0, np, filter), c->stream);
-    for (size_t q = 0; q < c->frames.size() && e == hipSuccess; ++q)
-        e = launch_score(c->frames[q]->score_launch(words, sums, p0, np, filter), c->stream);
+hipError_t launch_score_frames(smc_ctx *c, const float *words, unsigned long long *sums, uint32_t *hist,
+                               uint32_t p0, uint32_t np, bool filter) {
+    const bool mi = c->p.score == SMC_SCORE_MI;
+    ScoreLaunch L = c->score_launch(words, sums, p0, np, filter);
+    if (mi) L.hist = hist;
+    hipError_t e = launch_score(L, c->stream);
+    for (size_t q = 0; q < c->frames.size() && e == hipSuccess; ++q) {
+        ScoreLaunch F = c->frames[q]->score_launch(words, sums, p0, np, filter);
+        if (mi) F.hist = hist;
+        e = launch_score(F, c->stream);
+    }
+    // mutual information: the pooled histograms become scores
+    if (mi && e == hipSuccess) e = launch_mi_finalize(hist, p0, np, sums, c->stream);
     return e;
 }
 
@@ -336,7 +356,7 @@ smc_status evaluate_device(smc_ctx *c, const double *x_dev, uint32_t n) {
     if (st != SMC_OK) return st;
     HIP_TRY(launch_words(x_dev, n, c->f.geom, c->f.nearest, c->w_eval, c->stream));
     HIP_TRY(launch_fill_u64(c->s_eval, 6ull * n, c->stream));
-    HIP_TRY(launch_score_frames(c, c->w_eval, c->s_eval, 0, n, false));
+    HIP_TRY(launch_score_frames(c, c->w_eval, c->s_eval, c->hist_eval, 0, n, false));
     return SMC_OK;
 }
 
@@ -472,6 +492,12 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
         (st = c->alloc(&f.trace_ess, K)) != SMC_OK || (st = c->alloc(&f.trace_est, 6ull * K)) != SMC_OK ||
         (st = c->alloc(&f.flags, 4)) != SMC_OK)
         return bail(st);
+    if (p->score == SMC_SCORE_MI) {
+        const uint64_t words = (uint64_t)kMiBins * kMiBins * (n + 1ull);
+        if ((st = c->alloc(&c->hist, words)) != SMC_OK) return bail(st);
+        if (launch_fill_u64((unsigned long long *)c->hist, words / 2, c->stream) != hipSuccess)
+            return bail(fail(SMC_EDEVICE, "histogram clear failed"));
+    }
     if ((st = launch_prior(c)) != SMC_OK) return bail(st);
     *out = c;
     return SMC_OK;
@@ -497,10 +523,10 @@ smc_status smc_step(smc_ctx *c, uint32_t n_iters) {
     for (uint32_t it = 0; it < n_iters; ++it) {
         const uint32_t k = c->k_done + 1;
         hipError_t e = timed(c, c->ev_score,
-                             [&] { return launch_score_frames(c, c->f.words, c->f.sums, 0, c->f.n + 1, true); });
+                             [&] { return launch_score_frames(c, c->f.words, c->f.sums, c->hist, 0, c->f.n + 1, true); });
         if (e == hipSuccess) e = timed(c, c->ev_filter, [&] { return launch_filter(c->f, k, c->stream); });
         if (e == hipSuccess && k == c->f.n_iters) {
-            e = launch_score_frames(c, c->f.words, c->f.sums, c->f.n, 1, true);
+            e = launch_score_frames(c, c->f.words, c->f.sums, c->hist, c->f.n, 1, true);
             if (e == hipSuccess) e = launch_ghost_final(c->f, c->stream);
         }
         if (e != hipSuccess) return c->mark(fail(SMC_EDEVICE, "iteration %u launch failed: %s", k, hipGetErrorString(e)));
@@ -511,6 +537,7 @@ smc_status smc_step(smc_ctx *c, uint32_t n_iters) {
 
 smc_status smc_evaluate(smc_ctx *c, const double *states, uint32_t n, int64_t *moments) {
     if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (c->p.score == SMC_SCORE_MI) return fail(SMC_EINVAL, "the MI score has no moments; use smc_score_particles");
     if (n == 0) return SMC_OK;
     if (!states || !moments) return fail(SMC_EINVAL, "states and moments must not be NULL");
     for (uint64_t q = 0; q < 6ull * n; ++q)
@@ -525,6 +552,26 @@ smc_status smc_evaluate(smc_ctx *c, const double *states, uint32_t n, int64_t *m
     if (hipMemcpyAsync(moments, c->s_eval, 48ull * n, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
         return c->mark(fail(SMC_EDEVICE, "evaluation failed: %s", hipGetErrorString(hipGetLastError())));
+    return SMC_OK;
+}
+
+smc_status smc_score_particles(smc_ctx *c, const double *states, uint32_t n, double *scores) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (n == 0) return SMC_OK;
+    if (!states || !scores) return fail(SMC_EINVAL, "states and scores must not be NULL");
+    for (uint64_t q = 0; q < 6ull * n; ++q)
+        if (!isfinite(states[q])) return fail(SMC_EINVAL, "state %llu is not finite", (unsigned long long)q);
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    if ((st = ensure_eval(c, n)) != SMC_OK) return c->mark(st);
+    if (hipMemcpyAsync(c->x_eval, states, 48ull * n, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return c->mark(fail(SMC_EDEVICE, "upload of states failed"));
+    if ((st = evaluate_device(c, c->x_eval, n)) != SMC_OK) return c->mark(st);
+    if (launch_scores_from_sums(c->s_eval, n, c->f.sc, c->z_eval, c->stream) != hipSuccess ||
+        hipMemcpyAsync(scores, c->z_eval, 8ull * n, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return c->mark(fail(SMC_EDEVICE, "scoring failed: %s", hipGetErrorString(hipGetLastError())));
     return SMC_OK;
 }
 
@@ -555,7 +602,7 @@ smc_status smc_exhaustive(smc_ctx *c, const double lo[6], const double step[6], 
         HIP_TRY(launch_grid_words(lo, step, count, first, n, c->f.geom, c->f.nearest, c->x_eval, c->w_eval,
                                   c->stream));
         HIP_TRY(launch_fill_u64(c->s_eval, 6ull * n, c->stream));
-        HIP_TRY(launch_score_frames(c, c->w_eval, c->s_eval, 0, n, true));
+        HIP_TRY(launch_score_frames(c, c->w_eval, c->s_eval, c->hist_eval, 0, n, true));
         HIP_TRY(launch_chunk_best(c->s_eval, n, first, c->f.sc, dscores ? dscores + first : nullptr, dz + q, di + q,
                                   c->stream));
     }
@@ -793,7 +840,7 @@ smc_status smc_set_tuning(smc_ctx *c, int32_t layout, int32_t pt, int32_t tile_d
 
 namespace {
 struct TuneKey {
-    int mode;
+    int mode, score;
     int32_t sn[3], tn[3];
     bool sok, tfov;
     uint32_t n;
@@ -824,6 +871,7 @@ smc_status smc_autotune(smc_ctx *c, uint32_t reps, double *best_ms) {
     TuneKey key;
     std::memset(&key, 0, sizeof key);
     key.mode = c->mode;
+    key.score = c->p.score;
     for (int d = 0; d < 3; ++d) {
         key.sn[d] = c->sn[d];
         key.tn[d] = c->tn[d];
@@ -856,7 +904,8 @@ smc_status smc_autotune(smc_ctx *c, uint32_t reps, double *best_ms) {
         for (int pt : {4, 8})
             for (int q = 0; q < nd && result == SMC_OK && layout_fits(lay, c->sn); ++q) {
                 if ((result = smc_set_tuning(c, lay, pt, depths[q])) != SMC_OK) break;
-                const ScoreLaunch L = c->score_launch(c->f.words, c->s_eval, 0, np, true);
+                ScoreLaunch L = c->score_launch(c->f.words, c->s_eval, 0, np, true);
+                if (c->p.score == SMC_SCORE_MI) L.hist = c->hist_eval;
                 double tot = 0.0;
                 for (uint32_t r = 0; r <= reps && result == SMC_OK; ++r) {
                     float ms = 0.0f;
@@ -872,6 +921,11 @@ smc_status smc_autotune(smc_ctx *c, uint32_t reps, double *best_ms) {
             }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    // the timed launches left counts in the evaluation histograms
+    if (result == SMC_OK && c->hist_eval &&
+        launch_fill_u64((unsigned long long *)c->hist_eval, (uint64_t)kMiBins * kMiBins * c->eval_cap / 2,
+                        c->stream) != hipSuccess)
+        result = fail(SMC_EDEVICE, "histogram clear failed");
     if (result != SMC_OK) return c->mark(result);
     if ((st = smc_set_tuning(c, best.layout, best.pt, best.zchunk)) != SMC_OK) return st;
     {
@@ -1103,13 +1157,12 @@ smc_status record_run(smc_batch *b) {
         for (int q = 0; q < 4; ++q) HIP_TRY(launch_batch_score(b->cls[q].plan, k, b->stream));
         for (uint32_t i : b->singles) {
             smc_ctx *c = b->pairs[i];
-            if (k <= c->f.n_iters)
-                HIP_TRY(launch_score(c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true), b->stream));
+            if (k <= c->f.n_iters) HIP_TRY(launch_score_frames(c, c->f.words, c->f.sums, c->hist, 0, c->f.n + 1, true));
         }
         HIP_TRY(launch_filter_batch(b->states_dev, (uint32_t)b->pairs.size(), k, b->stream));
         for (smc_ctx *c : b->pairs)
             if (c->f.n_iters == k) {
-                HIP_TRY(launch_score(c->score_launch(c->f.words, c->f.sums, c->f.n, 1, true), b->stream));
+                HIP_TRY(launch_score_frames(c, c->f.words, c->f.sums, c->hist, c->f.n, 1, true));
                 HIP_TRY(launch_ghost_final(c->f, b->stream));
             }
     }
@@ -1153,7 +1206,7 @@ smc_status smc_batch_init(smc_batch **out, uint32_t n_pairs, const smc_volume *s
         b->kmax_all = std::max(b->kmax_all, c->f.n_iters);
         b->max_threads = std::max(b->max_threads, std::max(c->f.n, c->f.n_iters + 1));
         if (c->mode == kModeMask) b->cls[0].members.push_back(i);
-        else if (c->mode == kModeImageTrilinear) b->images.push_back(i);
+        else if (c->mode == kModeImageTrilinear && c->p.score != SMC_SCORE_MI) b->images.push_back(i);
         else b->singles.push_back(i);
     }
     // one layout / particles-per-group for all trilinear pairs: the first pair's

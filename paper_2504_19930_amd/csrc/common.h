@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 #define SMC_HD __host__ __device__ __forceinline__
 
@@ -126,7 +127,12 @@ SMC_HD void particle_words(const double p[6], const Geom &g, bool nearest, float
 
 // ---------------------------------------------------------------- scores
 
-enum ScoreKind : int32_t { kDice = 0, kNcc = 1, kSsd = 2 };
+enum ScoreKind : int32_t { kDice = 0, kNcc = 1, kSsd = 2, kMi = 3 };
+
+// Mutual information: joint-histogram bins per axis (source bin s_fx >> 11,
+// target bin t >> 3).  The finalised sums of an MI particle are
+// (overlap count, bits of the score as a double, 0, 0, 0, 0).
+constexpr int kMiBins = 32;
 
 struct ScoreConst {
     int32_t kind;
@@ -140,6 +146,12 @@ struct ScoreConst {
 // Similarity z (higher is better) of one particle from its exact sums;
 // -inf when an NCC / SSD overlap is below the minimum.
 SMC_HD double score_from_sums(const int64_t m[6], const ScoreConst &sc) {
+    if (sc.kind == kMi) {
+        if ((uint64_t)m[0] < sc.min_n) return -INFINITY;
+        double z;
+        memcpy(&z, &m[1], sizeof z);
+        return z;
+    }
     if (sc.kind == kDice) {
         const uint64_t a = (uint64_t)m[1], c = (uint64_t)m[2];
         const uint64_t den = a + sc.t_on;
@@ -170,6 +182,27 @@ SMC_HD double score_from_sums(const int64_t m[6], const ScoreConst &sc) {
     const double cst = sst - mu_t * ss - mu_s * st + n * mu_s * mu_t;
     const double tot = as * as * css + at * at * ctt - 2.0 * as * at * cst;
     return -(tot / n);
+}
+
+// Natural logarithm used by the MI score, identical on host and device: with
+// x = m 2^e, m in [sqrt(1/2), sqrt(2)), ln x = e ln 2 + 2 atanh(s) for
+// s = (m - 1) / (m + 1), the atanh series summed to the s^25 term (|s| <=
+// 0.172, error below 1e-20).  Library logarithms differ between platforms in
+// the last bit, which could move an integer resampling step.
+SMC_HD double mi_log(double x) {
+    int e;
+    double m = frexp(x, &e);
+    if (m < 0.7071067811865476) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0), s2 = s * s;
+    double t = s, acc = s;
+    for (int k = 3; k <= 25; k += 2) {
+        t = t * s2;
+        acc = acc + t / (double)k;
+    }
+    return (double)e * 0.6931471805599453 + 2.0 * acc;
 }
 
 // Measurement update: Gaussian in the deficit from the ideal score.

@@ -324,7 +324,87 @@ __global__ void k_ghost_final(const FilterState f) {
     for (int q = 0; q < 6; ++q) f.sums[6 * (size_t)f.n + q] = 0ull;
 }
 
+// One workgroup per particle: the histogram and its marginals (exact
+// integer counts) in LDS, then one thread forms the entropies in bin order
+// with mi_log, so the score is the same on every platform; 2 I / (H_s + H_t).
+__global__ __launch_bounds__(256) void k_mi_finalize(uint32_t *hist, uint32_t p0, unsigned long long *sums) {
+    constexpr int kHB = kMiBins * kMiBins;
+    __shared__ uint32_t h[kHB];
+    __shared__ unsigned long long marg[2 * kMiBins];
+    __shared__ unsigned long long total;
+    const uint32_t i = p0 + blockIdx.x;
+    uint32_t *hp = hist + (size_t)kHB * i;
+    const int tid = threadIdx.x;
+    if (tid < 2 * kMiBins) marg[tid] = 0ull;
+    if (tid == 0) total = 0ull;
+    __syncthreads();
+    unsigned long long mine = 0;
+    for (int q = tid; q < kHB; q += 256) {
+        const uint32_t v = hp[q];
+        h[q] = v;
+        hp[q] = 0u;  // ready for the next evaluation
+        mine += v;
+        if (v) {
+            atomicAdd(&marg[q / kMiBins], (unsigned long long)v);
+            atomicAdd(&marg[kMiBins + q % kMiBins], (unsigned long long)v);
+        }
+    }
+    atomicAdd(&total, mine);
+    __syncthreads();
+    if (tid != 0) return;
+    const unsigned long long n = total;
+    double z = 0.0;
+    if (n) {
+        const double N = (double)n;
+        double hs = 0.0, ht = 0.0, hst = 0.0;
+        for (int a = 0; a < kMiBins; ++a) {
+            if (marg[a]) {
+                const double f = (double)marg[a] / N;
+                hs = hs - f * mi_log(f);
+            }
+            if (marg[kMiBins + a]) {
+                const double f = (double)marg[kMiBins + a] / N;
+                ht = ht - f * mi_log(f);
+            }
+        }
+        for (int q = 0; q < kHB; ++q)
+            if (h[q]) {
+                const double f = (double)h[q] / N;
+                hst = hst - f * mi_log(f);
+            }
+        if (hs + ht > 0.0) z = 2.0 * (hs + ht - hst) / (hs + ht);
+    }
+    unsigned long long bits;
+    memcpy(&bits, &z, sizeof bits);
+    unsigned long long *o = sums + 6 * (size_t)i;
+    o[0] = n;
+    o[1] = bits;
+    o[2] = o[3] = o[4] = o[5] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_scores_from_sums(const unsigned long long *sums, uint32_t n,
+                                                          const ScoreConst sc, double *z) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t m[6];
+    for (int q = 0; q < 6; ++q) m[q] = (int64_t)sums[6 * (size_t)i + q];
+    z[i] = score_from_sums(m, sc);
+}
+
 }  // namespace
+
+hipError_t launch_mi_finalize(uint32_t *hist, uint32_t p0, uint32_t np, unsigned long long *sums, hipStream_t s) {
+    if (np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mi_finalize, dim3(np), dim3(256), 0, s, hist, p0, sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_scores_from_sums(const unsigned long long *sums, uint32_t n, const ScoreConst &sc, double *z,
+                                   hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scores_from_sums, dim3((n + 255) / 256), dim3(256), 0, s, sums, n, sc, z);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;

@@ -37,6 +37,9 @@ struct ScoreLaunch {
     unsigned long long *sums; // 6 per particle
     int32_t sn[3], tn[3];
     uint32_t p0, np;
+    // mutual information: the launch adds into kMiBins^2 counts per particle
+    // (indexed like words) instead of the moments
+    uint32_t *hist = nullptr;
 };
 
 hipError_t launch_score(const ScoreLaunch &L, hipStream_t s);
@@ -129,6 +132,13 @@ hipError_t launch_filter(const FilterState &f, uint32_t k, hipStream_t s);
 hipError_t launch_ghost_final(const FilterState &f, hipStream_t s);
 hipError_t launch_words(const double *x, uint32_t n, const Geom &g, bool nearest, float *words, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, hipStream_t s);
+// Mutual information: scores of particles p0 .. p0 + np - 1 from their joint
+// histograms into their sums (overlap count, score bits), clearing the
+// histograms for the next evaluation.
+hipError_t launch_mi_finalize(uint32_t *hist, uint32_t p0, uint32_t np, unsigned long long *sums, hipStream_t s);
+// Final scores of n particles from their sums.
+hipError_t launch_scores_from_sums(const unsigned long long *sums, uint32_t n, const ScoreConst &sc, double *z,
+                                   hipStream_t s);
 
 // Learned proposal network (cnn.hip).
 extern const int kCnnChannels[5];

@@ -49,6 +49,8 @@ struct KArgs {
     // packed layouts: byte size of the packed source and byte strides of its
     // rows and slices (32-bit buffer offsets; the host checks they fit)
     uint32_t src_bytes, ysb, zsb;
+    // mutual information: per-particle joint histograms, kMiBins^2 counts each
+    uint32_t *hist;
 };
 
 // Word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format,
@@ -372,12 +374,23 @@ struct Sums6 {
 // sampled source value in units of 1/256 (exact: s_fx = floor(256 s + 0.5)).
 // TRI: trilinear (inside iff 0 <= u <= n - 1 and the eight corners in the
 // source FOV); otherwise nearest (the words carry the +0.5 shift).
-template <int PT, int LAYOUT, bool TRI, int VMODE>
+// ACC 0: the six moments (NCC / SSD); ACC 1 (trilinear only): the joint
+// histogram of the mutual-information score, counted in LDS per workgroup and
+// added to the particle's histogram in global memory (bins left at zero are
+// skipped).
+template <int PT, int LAYOUT, bool TRI, int VMODE, int ACC = 0>
 __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t by) {
     constexpr bool SOK = VMODE == 1;
+    constexpr bool HIST = ACC == 1;
+    constexpr int kHB = kMiBins * kMiBins;
+    __shared__ uint32_t lhist[HIST ? PT : 1][HIST ? kHB : 1];
     const Tile t = tile_of<PT>(a, bx, by);
     const uint32_t live = live_mask<PT>(a, t, bx);
     if (live == 0u) return;  // every sample of this tile falls outside the source
+    if constexpr (HIST) {
+        for (uint32_t q = threadIdx.x; q < (uint32_t)(PT * kHB); q += kThreads) lhist[q / kHB][q % kHB] = 0u;
+        __syncthreads();
+    }
     float mx[PT], my[PT], mz[PT], ax[PT], ay[PT], az[PT];
     column_terms<PT>(a, t, mx, my, mz, ax, ay, az);
     Sums6 acc[PT];
@@ -486,11 +499,15 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                     const uint32_t sfx0 = (uint32_t)fmaf(sv, 256.0f, 0.5f);
                     const bool valid = in[p] & (okv[p] != 0u);
                     const uint32_t sfx = valid ? sfx0 : 0u;
-                    nt[p] += valid ? nt1 : 0u;
-                    acc[p].s += sfx;
-                    acc[p].ss += (unsigned long long)sfx * sfx;
-                    acc[p].tt += valid ? tv2 : 0u;
-                    acc[p].st += __umul24(sfx, tv);  // s_fx < 2^16, t < 2^8
+                    if constexpr (HIST) {
+                        if (valid) atomicAdd(&lhist[p][(sfx0 >> 11) * kMiBins + (tv >> 3)], 1u);
+                    } else {
+                        nt[p] += valid ? nt1 : 0u;
+                        acc[p].s += sfx;
+                        acc[p].ss += (unsigned long long)sfx * sfx;
+                        acc[p].tt += valid ? tv2 : 0u;
+                        acc[p].st += __umul24(sfx, tv);  // s_fx < 2^16, t < 2^8
+                    }
                 }
             } else if (TRI) {
                 // raw bytes: eight gathers per sample through 64-bit addresses
@@ -535,11 +552,15 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                     const uint32_t sfx0 = (uint32_t)fmaf(sv, 256.0f, 0.5f);
                     const bool valid = in[p] & (okv[p] != 0u);
                     const uint32_t sfx = valid ? sfx0 : 0u;
-                    nt[p] += valid ? nt1 : 0u;
-                    acc[p].s += sfx;
-                    acc[p].ss += (unsigned long long)sfx * sfx;
-                    acc[p].tt += valid ? tv2 : 0u;
-                    acc[p].st += sfx * tv;
+                    if constexpr (HIST) {
+                        if (valid) atomicAdd(&lhist[p][(sfx0 >> 11) * kMiBins + (tv >> 3)], 1u);
+                    } else {
+                        nt[p] += valid ? nt1 : 0u;
+                        acc[p].s += sfx;
+                        acc[p].ss += (unsigned long long)sfx * sfx;
+                        acc[p].tt += valid ? tv2 : 0u;
+                        acc[p].st += sfx * tv;
+                    }
                 }
             } else {
 #pragma unroll
@@ -570,6 +591,14 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
             acc[p].n += nt[p] & 511u;
             acc[p].t += nt[p] >> 9;
         }
+    }
+    if constexpr (HIST) {
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < (uint32_t)(PT * kHB); q += kThreads) {
+            const uint32_t p = q / kHB, b = q % kHB, v = lhist[p][b];
+            if (v != 0u && (int)p < t.npg) atomicAdd(a.hist + (size_t)kHB * (t.pbase + p) + b, v);
+        }
+        return;
     }
     __shared__ unsigned long long red[kWaves][PT][6];
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -625,11 +654,11 @@ __global__ __launch_bounds__(kThreads) void k_score_mask(const KArgs a) {
     mask_body<PT>(a, bx, by);
 }
 
-template <int PT, int LAYOUT, bool TRI, int VMODE>
+template <int PT, int LAYOUT, bool TRI, int VMODE, int ACC = 0>
 __global__ __launch_bounds__(kThreads) void k_score_image(const KArgs a) {
     uint32_t bx, by;
     xcd_order(blockIdx.x, gridDim.x, (a.np + PT - 1) / PT, &bx, &by);
-    image_body<PT, LAYOUT, TRI, VMODE>(a, bx, by);
+    image_body<PT, LAYOUT, TRI, VMODE, ACC>(a, bx, by);
 }
 
 // ---------------------------------------------------------------- batches
@@ -692,6 +721,7 @@ KArgs make_args(const ScoreLaunch &L, int pt, int *nz_chunks) {
     a.tgt_fov = L.tgt_fov;
     a.words = L.words;
     a.sums = L.sums;
+    a.hist = L.hist;
     a.sn0 = L.sn[0];
     a.sn1 = L.sn[1];
     a.sn2 = L.sn[2];
@@ -736,22 +766,22 @@ KArgs make_args(const ScoreLaunch &L, int pt, int *nz_chunks) {
 
 typedef void (*ScoreKernel)(const KArgs);
 
-template <int PT, int LAYOUT>
+template <int PT, int LAYOUT, int ACC>
 ScoreKernel pick_tri(int vmode) {
     if constexpr (LAYOUT != kLayoutRaw) {
-        if (vmode == 2) return k_score_image<PT, LAYOUT, true, 2>;
+        if (vmode == 2) return k_score_image<PT, LAYOUT, true, 2, ACC>;
     }
-    return vmode ? k_score_image<PT, LAYOUT, true, 1> : k_score_image<PT, LAYOUT, true, 0>;
+    return vmode ? k_score_image<PT, LAYOUT, true, 1, ACC> : k_score_image<PT, LAYOUT, true, 0, ACC>;
 }
 
-template <int PT>
+template <int PT, int ACC>
 ScoreKernel pick_tri_layout(int layout, int vmode) {
     switch (layout) {
-    case kLayoutPairX: return pick_tri<PT, kLayoutPairX>(vmode);
-    case kLayoutQuadXY: return pick_tri<PT, kLayoutQuadXY>(vmode);
-    case kLayoutOct: return pick_tri<PT, kLayoutOct>(vmode);
-    case kLayoutOctTile: return pick_tri<PT, kLayoutOctTile>(vmode);
-    default: return pick_tri<PT, kLayoutRaw>(vmode);
+    case kLayoutPairX: return pick_tri<PT, kLayoutPairX, ACC>(vmode);
+    case kLayoutQuadXY: return pick_tri<PT, kLayoutQuadXY, ACC>(vmode);
+    case kLayoutOct: return pick_tri<PT, kLayoutOct, ACC>(vmode);
+    case kLayoutOctTile: return pick_tri<PT, kLayoutOctTile, ACC>(vmode);
+    default: return pick_tri<PT, kLayoutRaw, ACC>(vmode);
     }
 }
 
@@ -761,7 +791,8 @@ ScoreKernel pick(const ScoreLaunch &L) {
     const bool sok = L.src_ok != nullptr;
     if (L.mode == kModeImageNearest)
         return sok ? k_score_image<PT, kLayoutRaw, false, 1> : k_score_image<PT, kLayoutRaw, false, 0>;
-    return pick_tri_layout<PT>(L.layout, !sok ? 0 : (L.has_sentinel ? 2 : 1));
+    const int vmode = !sok ? 0 : (L.has_sentinel ? 2 : 1);
+    return L.hist ? pick_tri_layout<PT, 1>(L.layout, vmode) : pick_tri_layout<PT, 0>(L.layout, vmode);
 }
 
 }  // namespace
