@@ -61,8 +61,9 @@ typedef enum { SMC_INTERP_NEAREST = 0, SMC_INTERP_TRILINEAR = 1 } smc_interp;
 
 /* How rotations are treated (the paper's own search is the BOX: Euler angles
  * in x0 +- limit, weighted-mean estimate).  WIDE is for searches whose
- * rotation limits reach a half turn (views far apart, e.g. apical against
- * parasternal): the estimate's rotation is the normalised weighted sum of the
+ * rotation limits reach a half turn (views far apart, e.g. the apical to
+ * parasternal pairs of the Discussion, about (90, -180) degrees about y and
+ * z): the estimate's rotation is the normalised weighted sum of the
  * particles' unit quaternions, put on the hemisphere of the first particle of
  * largest weight, converted back to Euler angles within pi of x0; and every
  * rotation axis whose limit is >= pi wraps around the circle in the
