@@ -30,6 +30,7 @@ constexpr int kWX = 16;  // wave patch width (x); 64 / kWX rows
 static_assert(kTX % kWX == 0 && 64 % kWX == 0 && kTY % (64 / kWX) == 0, "waves must tile the 32 x 8 column");
 constexpr int kWaves = kThreads / 64;
 constexpr int kZChunkMax = 256;  // keeps every per-thread 32-bit sum below 2^32
+constexpr int kSlab = 32;        // target slices staged in LDS at a time
 
 struct KArgs {
     const uint8_t *src, *src_ok, *tgt, *tgt_fov;
@@ -88,6 +89,7 @@ __device__ __forceinline__ const SMC_CONSTANT_AS T *as_const(const T *p) {
 
 struct Tile {
     int i, j, k0, k1;
+    int x0, y0;  // tile origin (column of the workgroup's first thread)
     bool ok;
     uint32_t pbase;
     int npg;
@@ -105,8 +107,10 @@ __device__ __forceinline__ Tile tile_of(const KArgs &a, uint32_t bx, uint32_t by
     // each wave covers a kWX x (64 / kWX) patch of the tile: a squarer patch
     // maps to fewer source cache lines under rotation
     const int lane = (int)(threadIdx.x % 64), wave = (int)(threadIdx.x / 64);
-    t.i = tx * kTX + (wave % (kTX / kWX)) * kWX + lane % kWX;
-    t.j = ty * kTY + (wave / (kTX / kWX)) * (64 / kWX) + lane / kWX;
+    t.x0 = tx * kTX;
+    t.y0 = ty * kTY;
+    t.i = t.x0 + (wave % (kTX / kWX)) * kWX + lane % kWX;
+    t.j = t.y0 + (wave / (kTX / kWX)) * (64 / kWX) + lane / kWX;
     t.ok = t.i < a.tn0 && t.j < a.tn1;
     t.k0 = zc * a.zchunk;
     t.k1 = min(t.k0 + a.zchunk, a.tn2);
@@ -306,6 +310,53 @@ __device__ __forceinline__ void corners_buf(__amdgpu_buffer_rsrc_t rs, uint32_t 
     }
 }
 
+// The four x-lerps fma(fx, b - a, a) of a packed 2x2x2 neighbourhood (lo:
+// bytes v0..v3 of slice z, hi: v4..v7 of slice z + 1).  Each byte b becomes
+// the half 1024 + b with one byte permute (high byte 0x64); packed half
+// subtractions give b - a and a exactly (integers below 2048), and the mixed-
+// precision FMA forms f * (b - a) + a in FP32 with one rounding -- the same
+// value as the FP32 formula, in 3 operations per lerp instead of 4.
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ half2v as_half2(uint32_t u) {
+    half2v h;
+    __builtin_memcpy(&h, &u, sizeof h);
+    return h;
+}
+
+__device__ __forceinline__ void x_lerps(uint32_t lo, uint32_t hi, float f, float &x00, float &x10, float &x01,
+                                        float &x11) {
+    constexpr uint32_t kMagic = 0x64646464u;
+    const half2v a0 = as_half2(__builtin_amdgcn_perm(kMagic, lo, 0x04020400u));  // (v0, v2)
+    const half2v b0 = as_half2(__builtin_amdgcn_perm(kMagic, lo, 0x04030401u));  // (v1, v3)
+    const half2v a1 = as_half2(__builtin_amdgcn_perm(kMagic, hi, 0x04020400u));  // (v4, v6)
+    const half2v b1 = as_half2(__builtin_amdgcn_perm(kMagic, hi, 0x04030401u));  // (v5, v7)
+    const half2v k1024 = {(_Float16)1024.0f, (_Float16)1024.0f};
+    const half2v d0 = b0 - a0, d1 = b1 - a1;
+    const half2v v0 = a0 - k1024, v1 = a1 - k1024;
+    x00 = fmaf(f, (float)d0.x, (float)v0.x);
+    x10 = fmaf(f, (float)d0.y, (float)v0.y);
+    x01 = fmaf(f, (float)d1.x, (float)v1.x);
+    x11 = fmaf(f, (float)d1.y, (float)v1.y);
+}
+
+// Raw packed corner words (quads and octets): lo = slice z, hi = slice z + 1.
+template <int LAYOUT>
+__device__ __forceinline__ void corner_words(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t dz, uint32_t &lo,
+                                             uint32_t &hi, uint64_t sentinel, bool &sent_ok) {
+    if (LAYOUT == kLayoutQuadXY) {
+        lo = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+        hi = __builtin_amdgcn_raw_buffer_load_b32(rs, off + dz, 0, 0);
+        const uint32_t st = (uint32_t)sentinel;
+        sent_ok = (lo != st) & (hi != st);
+    } else {
+        const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+        lo = w.x;
+        hi = w.y;
+        sent_ok = (lo != (uint32_t)sentinel) | (hi != (uint32_t)(sentinel >> 32));
+    }
+}
+
 // The eight trilinear corners of base voxel (ix, iy, iz) as floats, read from
 // one of the source layouts (corners beyond the last voxel repeat it; their
 // weight is zero there):
@@ -399,9 +450,8 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
         acc[p].n = acc[p].s = acc[p].t = acc[p].tt = acc[p].st = 0u;
         acc[p].ss = 0ull;
     }
-    if (t.ok) {
-        const size_t plane = (size_t)a.tn0 * (size_t)a.tn1;
-        const size_t tofs0 = (size_t)t.i + (size_t)a.tn0 * (size_t)t.j;
+    {
+        const uint32_t plane = (uint32_t)a.tn0 * (uint32_t)a.tn1;
         const uint32_t sn0 = (uint32_t)a.sn0, sn01 = (uint32_t)a.sn0 * (uint32_t)a.sn1;
         const float ex = (float)(a.sn0 - 1), ey = (float)(a.sn1 - 1), ez = (float)(a.sn2 - 1);
         const bool tfov = a.tgt_fov != nullptr;
@@ -418,21 +468,48 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
         uint32_t nt[PT];
 #pragma unroll
         for (int p = 0; p < PT; ++p) nt[p] = 0u;
-        // target bytes through buffer loads with 32-bit offsets (a volume has
-        // fewer than 2^31 voxels); the byte of the next slice is loaded one
-        // step ahead (past the last slice the bounds check returns zero)
+        // The target column block is staged in LDS a slab of kSlab slices at a
+        // time with coalesced loads (four bytes per lane where rows are 4-byte
+        // aligned): a gather costs the same whatever its width, and the
+        // per-slice target byte would otherwise be a fifth of the gathers.
+        // Loads past the volume's end read zero (bounds-checked buffer loads)
+        // and land only in slots of threads outside the target.
         const int tbytes = a.tn0 * a.tn1 * a.tn2;
         const __amdgpu_buffer_rsrc_t rs_t =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(a.tgt), (short)0, tbytes, kBufferWord3);
         const __amdgpu_buffer_rsrc_t rs_tf = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<uint8_t *>(a.tgt_fov), (short)0, tfov ? tbytes : 0, kBufferWord3);
-        const uint32_t plane32 = (uint32_t)plane;
-        uint32_t tofs = (uint32_t)tofs0 + plane32 * (uint32_t)t.k0;
-        uint32_t tv_next = __builtin_amdgcn_raw_buffer_load_b8(rs_t, tofs, 0, 0);
-        for (int k = t.k0; k < t.k1; ++k, tofs += plane32) {
-            const uint32_t tv = tv_next;
-            tv_next = __builtin_amdgcn_raw_buffer_load_b8(rs_t, tofs + plane32, 0, 0);
-            if (tfov && __builtin_amdgcn_raw_buffer_load_b8(rs_tf, tofs, 0, 0) == 0) continue;
+        __shared__ uint32_t tslab[kSlab * kThreads / 4], fslab[kSlab * kThreads / 4];
+        const uint8_t *tslab8 = (const uint8_t *)tslab, *fslab8 = (const uint8_t *)fslab;
+        const uint32_t col = (uint32_t)(t.j - t.y0) * kTX + (uint32_t)(t.i - t.x0);
+        const bool aligned = (a.tn0 & 3) == 0;
+        for (int kb = t.k0; kb < t.k1; kb += kSlab) {
+            const int ke = min(kb + kSlab, t.k1);
+            const uint32_t base = plane * (uint32_t)kb + (uint32_t)a.tn0 * (uint32_t)t.y0 + (uint32_t)t.x0;
+            __syncthreads();  // every thread is done with the previous slab
+            if (aligned) {
+                const uint32_t words = (uint32_t)(ke - kb) * (kThreads / 4);
+                for (uint32_t d = threadIdx.x; d < words; d += kThreads) {
+                    const uint32_t z = d / (kThreads / 4), r = (d / (kTX / 4)) % kTY, c = d % (kTX / 4);
+                    const uint32_t o = base + plane * z + (uint32_t)a.tn0 * r + 4u * c;
+                    tslab[d] = __builtin_amdgcn_raw_buffer_load_b32(rs_t, o, 0, 0);
+                    if (tfov) fslab[d] = __builtin_amdgcn_raw_buffer_load_b32(rs_tf, o, 0, 0);
+                }
+            } else {
+                const uint32_t bytes = (uint32_t)(ke - kb) * kThreads;
+                for (uint32_t b = threadIdx.x; b < bytes; b += kThreads) {
+                    const uint32_t z = b / kThreads, r = (b / kTX) % kTY, c = b % kTX;
+                    const uint32_t o = base + plane * z + (uint32_t)a.tn0 * r + c;
+                    ((uint8_t *)tslab)[b] = (uint8_t)__builtin_amdgcn_raw_buffer_load_b8(rs_t, o, 0, 0);
+                    if (tfov) ((uint8_t *)fslab)[b] = (uint8_t)__builtin_amdgcn_raw_buffer_load_b8(rs_tf, o, 0, 0);
+                }
+            }
+            __syncthreads();
+            if (!t.ok) continue;
+        for (int k = kb; k < ke; ++k) {
+            const uint32_t sidx = (uint32_t)(k - kb) * kThreads + col;
+            const uint32_t tv = tslab8[sidx];
+            if (tfov && fslab8[sidx] == 0) continue;
             const uint32_t tv2 = tv * tv;
             const uint32_t nt1 = 1u + (tv << 9);
             const float fk = (float)k;
@@ -477,21 +554,29 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                 }
                 uint32_t okv[PT];
                 float v[PT][8];
+                uint32_t wlo[PT], whi[PT];
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
                     bool sent_ok;
-                    corners_buf<LAYOUT>(rs, off[p], LAYOUT == kLayoutPairX ? ddy[p] : 0u,
-                                        LAYOUT == kLayoutPairX || LAYOUT == kLayoutQuadXY ? ddz[p] : 0u, v[p],
-                                        a.sentinel, sent_ok);
+                    if constexpr (LAYOUT == kLayoutPairX)
+                        corners_buf<LAYOUT>(rs, off[p], ddy[p], ddz[p], v[p], a.sentinel, sent_ok);
+                    else
+                        corner_words<LAYOUT>(rs, off[p], LAYOUT == kLayoutQuadXY ? ddz[p] : 0u, wlo[p], whi[p],
+                                             a.sentinel, sent_ok);
                     okv[p] = SOK ? __builtin_amdgcn_raw_buffer_load_b8(rs_ok, vidx[p], 0, 0)
                                  : (VMODE == 2 ? (sent_ok ? 1u : 0u) : 1u);
                 }
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
-                    const float x00 = fmaf(fxa[p], v[p][1] - v[p][0], v[p][0]);
-                    const float x10 = fmaf(fxa[p], v[p][3] - v[p][2], v[p][2]);
-                    const float x01 = fmaf(fxa[p], v[p][5] - v[p][4], v[p][4]);
-                    const float x11 = fmaf(fxa[p], v[p][7] - v[p][6], v[p][6]);
+                    float x00, x10, x01, x11;
+                    if constexpr (LAYOUT == kLayoutPairX) {
+                        x00 = fmaf(fxa[p], v[p][1] - v[p][0], v[p][0]);
+                        x10 = fmaf(fxa[p], v[p][3] - v[p][2], v[p][2]);
+                        x01 = fmaf(fxa[p], v[p][5] - v[p][4], v[p][4]);
+                        x11 = fmaf(fxa[p], v[p][7] - v[p][6], v[p][6]);
+                    } else {
+                        x_lerps(wlo[p], whi[p], fxa[p], x00, x10, x01, x11);
+                    }
                     const float y0 = fmaf(fya[p], x10 - x00, x00);
                     const float y1 = fmaf(fya[p], x11 - x01, x01);
                     const float sv = fmaf(fza[p], y1 - y0, y0);
@@ -586,6 +671,7 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                 }
             }
         }
+        }  // slabs
 #pragma unroll
         for (int p = 0; p < PT; ++p) {
             acc[p].n += nt[p] & 511u;
@@ -654,8 +740,15 @@ __global__ __launch_bounds__(kThreads) void k_score_mask(const KArgs a) {
     mask_body<PT>(a, bx, by);
 }
 
+// The octet variants with four particles per workgroup fit 72 VGPRs without
+// spilling: ask for the seven waves per SIMD that allows.
+template <int PT, int LAYOUT, int VMODE, int ACC>
+constexpr int kImageWaves =
+    PT == 4 && (LAYOUT == kLayoutOct || LAYOUT == kLayoutOctTile) && VMODE != 1 && ACC == 0 ? 7 : 1;
+
 template <int PT, int LAYOUT, bool TRI, int VMODE, int ACC = 0>
-__global__ __launch_bounds__(kThreads) void k_score_image(const KArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kImageWaves<PT, LAYOUT, VMODE, ACC>)))
+void k_score_image(const KArgs a) {
     uint32_t bx, by;
     xcd_order(blockIdx.x, gridDim.x, (a.np + PT - 1) / PT, &bx, &by);
     image_body<PT, LAYOUT, TRI, VMODE, ACC>(a, bx, by);
