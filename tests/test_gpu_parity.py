@@ -368,6 +368,45 @@ def test_batch_pairs_equal_single_runs_across_replays(smc, orc):
     b.close()
 
 
+def test_batch_with_mi_and_wide_pairs(smc, orc):
+    """A batch mixing a moment-based image pair, an MI pair (run as its own
+    launches inside the graph) and a wide-rotation mask pair: each equals its
+    single-context run bit for bit over two replays, and the MI pair the
+    oracle."""
+    import math
+    img = synth.speckle_pair(side=36, seed=41, trans=3.0)
+    mi = synth.speckle_pair(side=34, seed=42, trans=3.0)
+    gt = np.array([0.05, -0.03, math.radians(178.0), 1.0, -1.0, 0.5])
+    wide = synth.mask_pair((36, 36, 36), outer=(9.0, 6.0, 4.5), inner=None, gt=gt, centre=(23.5, 20.5, 19.5))
+    host = [(img, config.default_params("ncc", 70, 3, 20.0, 3.0, seed=5, pair_id=0)),
+            (mi, config.default_params("mi", 50, 4, 20.0, 3.0, seed=6, pair_id=1)),
+            (wide, dict(config.default_params("dice", 90, 5, 10.0, 3.0, seed=7, pair_id=2), rotation_mode="wide"))]
+    host[2][1]["limit"][2] = math.pi
+    pairs = []
+    for pr, prm in host:
+        q = dict(src=dev(pr["src"]), tgt=dev(pr["tgt"]), params=prm)
+        if "src_fov" in pr:
+            q["src_fov"] = dev(pr["src_fov"])
+        pairs.append(q)
+    b = smc.Batch(pairs)
+    for rep in range(2):
+        seeds = [50 + 10 * rep + i for i in range(3)]
+        b.set_seeds(seeds)
+        b.run()
+        for i, (pr, prm) in enumerate(host):
+            r = _reg(smc, pr, dict(prm, seed=seeds[i]), src_fov=pr.get("src_fov"))
+            r.run()
+            assert np.array_equal(b.particles(i)["states"], r.particles()["states"]), (rep, i)
+            assert np.array_equal(b.particles(i)["ancestors"], r.particles()["ancestors"]), (rep, i)
+            assert np.array_equal(b.trace(i)["score"], r.trace()["score"]), (rep, i)
+            assert np.array_equal(b.estimate(i)["params"], r.estimate()["params"]), (rep, i)
+            r.close()
+        o = orc.smc_run(orc.Volume(mi["src"], fov=mi["src_fov"]), orc.Volume(mi["tgt"]), dict(host[1][1], seed=seeds[1]))
+        assert np.array_equal(b.particles(1)["ancestors"], o["ancestors"])
+        assert np.array_equal(b.particles(1)["logw"], o["logw"])
+    b.close()
+
+
 def test_exhaustive_search_matches_oracle_grid(smc, orc):
     """The EX baseline: every grid score equals the oracle's (bit-exact Dice)
     and the argmax is the truth on the 5^6 grid of the brute-force pin."""
