@@ -174,6 +174,47 @@ __device__ __forceinline__ uint32_t live_mask(const KArgs &a, const Tile &t, uin
     return live;
 }
 
+// ---------------------------------------------------------------- target slabs
+
+// Stage target slices [kb, ke) of the workgroup's 32 x 8 column block (and
+// its FOV when given) in LDS: slot z * 256 + row * 32 + column.  Coalesced
+// 4-byte loads where rows are 4-byte aligned, bytes otherwise.  A gather
+// costs about the same whatever its width, so this replaces one byte gather
+// per thread and slice by a quarter of a coalesced load.  Loads past the
+// volume's end read zero (bounds-checked buffer loads) and fill only slots
+// of threads outside the target.
+__device__ __forceinline__ void stage_target(const KArgs &a, const Tile &t, int kb, int ke,
+                                             __amdgpu_buffer_rsrc_t rs_t, __amdgpu_buffer_rsrc_t rs_tf, bool tfov,
+                                             uint32_t *tslab, uint32_t *fslab) {
+    const uint32_t plane = (uint32_t)a.tn0 * (uint32_t)a.tn1;
+    const uint32_t base = plane * (uint32_t)kb + (uint32_t)a.tn0 * (uint32_t)t.y0 + (uint32_t)t.x0;
+    if ((a.tn0 & 3) == 0) {
+        const uint32_t words = (uint32_t)(ke - kb) * (kThreads / 4);
+        for (uint32_t d = threadIdx.x; d < words; d += kThreads) {
+            const uint32_t z = d / (kThreads / 4), r = (d / (kTX / 4)) % kTY, c = d % (kTX / 4);
+            const uint32_t o = base + plane * z + (uint32_t)a.tn0 * r + 4u * c;
+            tslab[d] = __builtin_amdgcn_raw_buffer_load_b32(rs_t, o, 0, 0);
+            if (tfov) fslab[d] = __builtin_amdgcn_raw_buffer_load_b32(rs_tf, o, 0, 0);
+        }
+    } else {
+        const uint32_t bytes = (uint32_t)(ke - kb) * kThreads;
+        for (uint32_t b = threadIdx.x; b < bytes; b += kThreads) {
+            const uint32_t z = b / kThreads, r = (b / kTX) % kTY, c = b % kTX;
+            const uint32_t o = base + plane * z + (uint32_t)a.tn0 * r + c;
+            ((uint8_t *)tslab)[b] = (uint8_t)__builtin_amdgcn_raw_buffer_load_b8(rs_t, o, 0, 0);
+            if (tfov) ((uint8_t *)fslab)[b] = (uint8_t)__builtin_amdgcn_raw_buffer_load_b8(rs_tf, o, 0, 0);
+        }
+    }
+}
+
+// floor and convert in one instruction (exact for the non-negative
+// coordinates whose results are used)
+__device__ __forceinline__ uint32_t floor_u32(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return (uint32_t)r;
+}
+
 // ---------------------------------------------------------------- masks
 
 // Source byte: bit 0 = inside the source FOV, bit 1 = mask on (and in FOV).
@@ -187,38 +228,61 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
     if (live == 0u) return;  // nothing of this tile can reach the source region
     float mx[PT], my[PT], mz[PT], ax[PT], ay[PT], az[PT];
     column_terms<PT>(a, t, mx, my, mz, ax, ay, az);
+    if constexpr (PT > 4) {
+        // the per-particle slopes are uniform; with many particles they would
+        // crowd the scalar registers out (and be spilled to vector lanes)
+#pragma unroll
+        for (int p = 0; p < PT; ++p) asm("" : "+v"(ax[p]), "+v"(ay[p]), "+v"(az[p]));
+    }
     uint32_t acc1[PT], acc2[PT];
 #pragma unroll
     for (int p = 0; p < PT; ++p) acc1[p] = acc2[p] = 0u;
-    if (t.ok) {
-        const size_t plane = (size_t)a.tn0 * (size_t)a.tn1;
-        const uint8_t *tp = a.tgt + (size_t)t.i + (size_t)a.tn0 * (size_t)t.j + plane * (size_t)t.k0;
-        const uint32_t sn01 = (uint32_t)a.sn0 * (uint32_t)a.sn1;
-        for (int k = t.k0; k < t.k1; ++k, tp += plane) {
-            const uint32_t tb = *tp;
-            const uint32_t keep = (tb & 1u) ? 3u : 0u;
-            const bool ton = (tb & 2u) != 0u;
-            const float fk = (float)k;
-            // addresses of all PT samples first (outside: a safe address, result
-            // masked), then every load, then the sums: the loads overlap
-            uint32_t addr[PT];
-            bool in[PT];
+    {
+        // prepared source bytes through a bounds-checked buffer with 32-bit
+        // offsets: an outside sample may form any offset, its result is masked
+        const uint32_t sn0 = (uint32_t)a.sn0, sn01 = (uint32_t)a.sn0 * (uint32_t)a.sn1;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t *>(a.src), (short)0, a.sn0 * a.sn1 * a.sn2, kBufferWord3);
+        // nearest (the words carry +0.5): inside iff 0 <= u < n, one unsigned
+        // compare of bit patterns per axis (coordinates are never -0)
+        const uint32_t nxb = __float_as_uint((float)a.sn0), nyb = __float_as_uint((float)a.sn1),
+                       nzb = __float_as_uint((float)a.sn2);
+        const __amdgpu_buffer_rsrc_t rs_t = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t *>(a.tgt), (short)0, a.tn0 * a.tn1 * a.tn2, kBufferWord3);
+        __shared__ uint32_t tslab[kSlab * kThreads / 4];
+        const uint8_t *tslab8 = (const uint8_t *)tslab;
+        const uint32_t col = (uint32_t)(t.j - t.y0) * kTX + (uint32_t)(t.i - t.x0);
+        for (int kb = t.k0; kb < t.k1; kb += kSlab) {
+            const int ke = min(kb + kSlab, t.k1);
+            __syncthreads();  // every thread is done with the previous slab
+            stage_target(a, t, kb, ke, rs_t, rs_t, false, tslab, tslab);
+            __syncthreads();
+            if (!t.ok) continue;
+            for (int k = kb; k < ke; ++k) {
+                const uint32_t tb = tslab8[(uint32_t)(k - kb) * kThreads + col];
+                const uint32_t keep = (tb & 1u) ? 3u : 0u;
+                const bool ton = (tb & 2u) != 0u;
+                const float fk = (float)k;
+                // offsets of all PT samples first, then every load, then the sums
+                // the inside flags travel as vector masks (keep & ~0 or 0): eight
+                // or more particles' lane masks would not fit the scalar registers
+                uint32_t off[PT], msk[PT];
 #pragma unroll
-            for (int p = 0; p < PT; ++p) {
-                const int ix = (int)floorf(fmaf(ax[p], fk, mx[p]));
-                const int iy = (int)floorf(fmaf(ay[p], fk, my[p]));
-                const int iz = (int)floorf(fmaf(az[p], fk, mz[p]));
-                in[p] = (uint32_t)ix < (uint32_t)a.sn0 && (uint32_t)iy < (uint32_t)a.sn1 &&
-                        (uint32_t)iz < (uint32_t)a.sn2;
-                addr[p] = in[p] ? (uint32_t)ix + (uint32_t)a.sn0 * (uint32_t)iy + sn01 * (uint32_t)iz : 0u;
-            }
-            uint32_t val[PT];
+                for (int p = 0; p < PT; ++p) {
+                    const float ux = fmaf(ax[p], fk, mx[p]);
+                    const float uy = fmaf(ay[p], fk, my[p]);
+                    const float uz = fmaf(az[p], fk, mz[p]);
+                    const bool in = ((live >> p) & 1u) & (__float_as_uint(ux) < nxb) & (__float_as_uint(uy) < nyb) &
+                                    (__float_as_uint(uz) < nzb);
+                    msk[p] = in ? keep : 0u;
+                    off[p] = floor_u32(ux) + __umul24(floor_u32(uy), sn0) + floor_u32(uz) * sn01;
+                }
+                uint32_t val[PT];
 #pragma unroll
-            for (int p = 0; p < PT; ++p) val[p] = (live >> p) & 1u ? a.src[addr[p]] : 0u;
+                for (int p = 0; p < PT; ++p) val[p] = __builtin_amdgcn_raw_buffer_load_b8(rs, off[p], 0, 0);
 #pragma unroll
-            for (int p = 0; p < PT; ++p) {
-                if ((live >> p) & 1u) {
-                    const uint32_t v = in[p] ? (val[p] & keep) : 0u;
+                for (int p = 0; p < PT; ++p) {
+                    const uint32_t v = val[p] & msk[p];
                     const uint32_t inc = (v & 1u) | ((v & 2u) << 15);
                     acc1[p] += inc;
                     acc2[p] += ton ? inc : 0u;
@@ -255,13 +319,6 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
 
 // ---------------------------------------------------------------- images
 
-// floor and convert in one instruction (exact for the clamped, non-negative
-// coordinates it is used on)
-__device__ __forceinline__ uint32_t floor_u32(float x) {
-    int r;
-    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
-    return (uint32_t)r;
-}
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
@@ -482,28 +539,10 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
         __shared__ uint32_t tslab[kSlab * kThreads / 4], fslab[kSlab * kThreads / 4];
         const uint8_t *tslab8 = (const uint8_t *)tslab, *fslab8 = (const uint8_t *)fslab;
         const uint32_t col = (uint32_t)(t.j - t.y0) * kTX + (uint32_t)(t.i - t.x0);
-        const bool aligned = (a.tn0 & 3) == 0;
         for (int kb = t.k0; kb < t.k1; kb += kSlab) {
             const int ke = min(kb + kSlab, t.k1);
-            const uint32_t base = plane * (uint32_t)kb + (uint32_t)a.tn0 * (uint32_t)t.y0 + (uint32_t)t.x0;
             __syncthreads();  // every thread is done with the previous slab
-            if (aligned) {
-                const uint32_t words = (uint32_t)(ke - kb) * (kThreads / 4);
-                for (uint32_t d = threadIdx.x; d < words; d += kThreads) {
-                    const uint32_t z = d / (kThreads / 4), r = (d / (kTX / 4)) % kTY, c = d % (kTX / 4);
-                    const uint32_t o = base + plane * z + (uint32_t)a.tn0 * r + 4u * c;
-                    tslab[d] = __builtin_amdgcn_raw_buffer_load_b32(rs_t, o, 0, 0);
-                    if (tfov) fslab[d] = __builtin_amdgcn_raw_buffer_load_b32(rs_tf, o, 0, 0);
-                }
-            } else {
-                const uint32_t bytes = (uint32_t)(ke - kb) * kThreads;
-                for (uint32_t b = threadIdx.x; b < bytes; b += kThreads) {
-                    const uint32_t z = b / kThreads, r = (b / kTX) % kTY, c = b % kTX;
-                    const uint32_t o = base + plane * z + (uint32_t)a.tn0 * r + c;
-                    ((uint8_t *)tslab)[b] = (uint8_t)__builtin_amdgcn_raw_buffer_load_b8(rs_t, o, 0, 0);
-                    if (tfov) ((uint8_t *)fslab)[b] = (uint8_t)__builtin_amdgcn_raw_buffer_load_b8(rs_tf, o, 0, 0);
-                }
-            }
+            stage_target(a, t, kb, ke, rs_t, rs_tf, tfov, tslab, fslab);
             __syncthreads();
             if (!t.ok) continue;
         for (int k = kb; k < ke; ++k) {
