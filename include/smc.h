@@ -39,7 +39,9 @@ typedef enum {
     SMC_EINVAL = -1,   /* bad argument (null pointer, size, NaN, unsupported combination) */
     SMC_ENOMEM = -2,   /* device allocation failed */
     SMC_EDEVICE = -3,  /* a HIP call or kernel launch failed */
-    SMC_ESTATE = -4    /* call not valid in the context's current state */
+    SMC_ESTATE = -4,   /* call not valid in the context's current state */
+    SMC_ENOOVERLAP = -5 /* smc_estimate: every particle of the latest iteration scored -inf (no overlap
+                           reached the minimum); the outputs are still written (uniform-weight mean) */
 } smc_status;
 
 /* Similarity used as the filter's measurement (Fig. 1 caption).
@@ -119,7 +121,8 @@ smc_status smc_step(smc_ctx *ctx, uint32_t n_iters);
 /* The estimate after the last completed iteration: parameters, the 3x4
  * target-mm -> source-mm matrix (row-major, Eq. 3 without its last row), the
  * estimate's own score and the effective sample size.  Any output may be
- * NULL.  Syncs. */
+ * NULL.  Syncs.  Returns SMC_ENOOVERLAP, with the outputs written, when the
+ * latest iteration's weights were all -inf. */
 smc_status smc_estimate(smc_ctx *ctx, double params[6], double mat3x4[12], double *score, double *ess);
 
 /* Host copies of the current particle set (N x 6), the log-weights of the

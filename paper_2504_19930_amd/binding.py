@@ -18,7 +18,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsmc.so")
 
-SMC_OK, SMC_EINVAL, SMC_ENOMEM, SMC_EDEVICE, SMC_ESTATE = 0, -1, -2, -3, -4
+SMC_OK, SMC_EINVAL, SMC_ENOMEM, SMC_EDEVICE, SMC_ESTATE, SMC_ENOOVERLAP = 0, -1, -2, -3, -4, -5
 SCORES = {"dice": 0, "ncc": 1, "ssd": 2, "mi": 3}
 INTERPS = {"nearest": 0, "trilinear": 1}
 ROTATIONS = {"box": 0, "wide": 1}
@@ -186,9 +186,11 @@ def smc_step(ctx, n_iters: int):
 def smc_estimate(ctx) -> dict:
     p, M = np.zeros(6), np.zeros(12)
     score, ess = C.c_double(), C.c_double()
-    _check(lib().smc_estimate(ctx, _ptr(p), _ptr(M), C.cast(C.byref(score), C.c_void_p),
-                              C.cast(C.byref(ess), C.c_void_p)))
-    return dict(params=p, matrix=M.reshape(3, 4), score=score.value, ess=ess.value)
+    st = lib().smc_estimate(ctx, _ptr(p), _ptr(M), C.cast(C.byref(score), C.c_void_p),
+                            C.cast(C.byref(ess), C.c_void_p))
+    if st != SMC_ENOOVERLAP:
+        _check(st)
+    return dict(params=p, matrix=M.reshape(3, 4), score=score.value, ess=ess.value, no_overlap=st == SMC_ENOOVERLAP)
 
 
 def smc_get_particles(ctx, n: int) -> dict:

@@ -644,7 +644,9 @@ smc_status smc_estimate(smc_ctx *c, double params[6], double mat3x4[12], double 
     if ((st = c->check_sticky()) != SMC_OK) return st;
     if ((st = set_device(c)) != SMC_OK) return c->mark(st);
     double est[6], sc = NAN, e = NAN;
+    int32_t flags[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(est, c->f.est, sizeof est, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(flags, c->f.flags, sizeof flags, hipMemcpyDeviceToHost, c->stream));
     if (c->k_done >= 1)
         HIP_TRY(hipMemcpyAsync(&e, c->f.trace_ess + (c->k_done - 1), sizeof e, hipMemcpyDeviceToHost, c->stream));
     if (c->k_done == c->f.n_iters)
@@ -659,6 +661,8 @@ smc_status smc_estimate(smc_ctx *c, double params[6], double mat3x4[12], double 
     if (mat3x4) rigid_matrix(est, c->f.geom, mat3x4);
     if (score) *score = sc;
     if (ess) *ess = e;
+    if (c->k_done >= 1 && flags[1])
+        return fail(SMC_ENOOVERLAP, "no particle reached the minimum overlap at iteration %u", c->k_done);
     return SMC_OK;
 }
 

@@ -103,6 +103,7 @@ __device__ __forceinline__ void init_body(const FilterState &f, uint32_t i, uint
         for (int d = 0; d < 6; ++d) f.est[d] = f.x0[d];
         particle_words(f.x0, f.geom, f.nearest, f.words + 12 * (size_t)f.n);
         f.flags[0] = 0;
+        f.flags[1] = 0;
     }
     const uint32_t nt = f.n_iters + 1;
     for (uint32_t q = i; q < nt; q += stride) {
@@ -234,6 +235,7 @@ __device__ __forceinline__ void filter_body(const FilterState &f, const uint32_t
         }
         f.trace_ess[k - 1] = (bcast[0] * bcast[0]) / bcast[1];
         if (degenerate) f.flags[0] = 1;
+        f.flags[1] = degenerate ? 1 : 0;  // the latest iteration's weights were all -inf
         particle_words(est, f.geom, f.nearest, f.words + 12 * (size_t)n);
     }
 

@@ -114,7 +114,7 @@ struct FilterState {
     double *trace_score;      // K + 1
     double *trace_ess;        // K
     double *trace_est;        // 6 K
-    int32_t *flags;           // [0] degenerate weights seen
+    int32_t *flags;           // [0] degenerate weights seen, [1] at the latest iteration
     // learned proposal: the prior draw comes from a Gaussian truncated to the
     // limits box, and the first update adds log p - log q (p uniform)
     int32_t has_proposal;

@@ -195,6 +195,10 @@ def test_degenerate_sizes(smc, orc):
     spk = synth.speckle_pair(side=16, seed=3, cone=False)
     r, o = _compare_runs(smc, orc, spk, far)
     assert o["degenerate"] and np.all(np.isfinite(r.particles()["states"]))
+    assert r.estimate()["no_overlap"]
+    st = smc.lib().smc_estimate(r.ctx, None, None, None, None)
+    assert st == smc.SMC_ENOOVERLAP and "overlap" in smc.lib().smc_last_error().decode()
+    assert not _reg(smc, spk, config.default_params("ncc", 16, 2, 10.0, 2.0, seed=1)).run()["no_overlap"]
 
 
 def test_stepwise_equals_single_call_and_state_roundtrip(smc, orc):
