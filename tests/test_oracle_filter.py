@@ -1,7 +1,8 @@
 """Pins of the oracle's filter steps (Fig. 1: update, estimation, resampling,
 prediction) and of the whole SMC (CPU only): invariants, exact integer
 properties of systematic resampling, Box-Muller statistics, brute force over
-a small transform grid and recovery of known synthetic transforms."""
+a small transform grid, a one-parameter filter against its posterior by
+quadrature, and recovery of known synthetic transforms."""
 
 import itertools
 from fractions import Fraction
@@ -111,6 +112,20 @@ def test_box_muller_normals(orc):
     assert not np.array_equal(orc.gauss6(11, 0, 5, 3), orc.gauss6(11, 0, 5, 4))  # iteration in counter
 
 
+def test_box_muller_ten_million_draws(orc):
+    """10^7 normals through the prediction step itself (unit width, no
+    annealing, limits far away, zero parents): pooled mean and variance
+    within 1e-3, normal by Kolmogorov-Smirnov, axes uncorrelated."""
+    n = 10_000_000 // 6 + 1
+    prm = dict(n_particles=n, n_iters=2, seed=2024, limit=[1e6] * 6, sigma0=[1.0] * 6, anneal=1.0,
+               sigma_score=0.1)
+    g = orc.perturb(prm, 1, np.zeros((n, 6)), np.arange(n, dtype=np.int32))
+    x = g.ravel()
+    assert abs(x.mean()) < 1e-3 and abs(x.var() - 1.0) < 1e-3
+    assert stats.kstest(x, "norm").pvalue > 0.01
+    assert np.abs(np.corrcoef(g.T) - np.eye(6)).max() < 5e-3
+
+
 def test_init_uniform_in_limits(orc):
     p = _params(n_particles=20000, x0=[0.1, -0.1, 0.0, 1.0, 2.0, -3.0])
     x = orc.init_particles(p)
@@ -156,6 +171,60 @@ def test_smc_deterministic(orc):
     b = orc.smc_run(pair["src"], pair["tgt"], p)
     assert np.array_equal(a["est"], b["est"]) and np.array_equal(a["states"], b["states"])
     assert np.array_equal(a["trace_score"], b["trace_score"])
+
+
+def _toy_pair(shift):
+    """24^3 smooth asymmetric blobs; the source is the target moved by
+    +shift voxels along x, so only t_x matters and its true value is shift."""
+    g = np.arange(24, dtype=float)
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+
+    def blob(xx):
+        return (40 + 150 * np.exp(-((xx - 11) ** 2 / 18.0 + (Y - 12) ** 2 / 32.0 + (Z - 12) ** 2 / 50.0))
+                + 30 * np.exp(-((xx - 16) ** 2 + (Y - 9) ** 2 + (Z - 14) ** 2) / 8.0))
+    return np.round(blob(X - shift)).astype(np.uint8), np.round(blob(X)).astype(np.uint8)
+
+
+def test_one_parameter_filter_matches_quadrature(orc):
+    """Only t_x free (limit 3 voxels, truth 2.4, so the prior box truncates
+    the posterior).  After one iteration the estimate is the self-normalised
+    importance-sampling mean of the posterior prior x likelihood; after two
+    it is the mean of likelihood x (reflected Gaussian prediction of the
+    first posterior).  Both are computed by quadrature on 2401 nodes from the
+    oracle's own scores and must agree within four Monte Carlo standard
+    errors; a likelihood with sigma^2 for 2 sigma^2 or without the square
+    moves the mean by more than ten."""
+    from scipy.stats import norm
+    src, tgt = _toy_pair(2.4)
+    L, s0, ss = 3.0, 0.5, 0.05
+    prm = dict(n_particles=16384, n_iters=1, seed=0, score="ncc", interp="trilinear", sigma_score=ss,
+               limit=[0, 0, 0, L, 0, 0], sigma0=[0, 0, 0, s0, 0, 0], anneal=0.9)
+    xs = np.linspace(-L, L, 2401)
+    st = np.zeros((len(xs), 6))
+    st[:, 3] = xs
+    z = orc.Problem(orc.Volume(src), orc.Volume(tgt)).score(prm, st)
+    ll = np.array([orc.loglik(v, "ncc", ss) for v in z])
+    lik = np.exp(ll - ll.max())
+
+    def mean_of(dens):
+        return np.trapezoid(xs * dens, xs) / np.trapezoid(dens, xs)
+    m1 = mean_of(lik)
+    p1 = lik / np.trapezoid(lik, xs)
+    ker = (norm.pdf(xs[:, None] - xs[None, :], scale=s0) + norm.pdf(2 * L - xs[:, None] - xs[None, :], scale=s0)
+           + norm.pdf(-2 * L - xs[:, None] - xs[None, :], scale=s0))
+    m2 = mean_of(lik * np.trapezoid(ker * p1[None, :], xs, axis=1))
+    for K, want in ((1, m1), (2, m2)):
+        for seed in (0, 1):
+            r = orc.smc_run(src, tgt, dict(prm, n_iters=K, seed=seed))
+            w = np.exp(r["logw"] - r["logw"].max())
+            w /= w.sum()
+            tx = r["states"][:, 3]
+            assert np.all(r["states"][:, [0, 1, 2, 4, 5]] == 0.0)
+            assert abs(np.sum(w * tx) - r["est"][3]) < 1e-12
+            se = np.sqrt(np.sum(w ** 2 * (tx - r["est"][3]) ** 2))
+            assert abs(r["est"][3] - want) < 4 * se, (K, seed, r["est"][3], want, se)
+    for wrong in (2 * ll, -(1 - z) / (2 * ss ** 2)):
+        assert abs(mean_of(np.exp(wrong - wrong.max())) - m1) > 10 * 0.007
 
 
 def test_smc_brute_force_grid(orc):
