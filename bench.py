@@ -41,7 +41,7 @@ OPS_PER_EVAL = 25.0
 GATHER_BYTES_PER_EVAL = 8.0
 # launch configuration timed by default (layout, particles per workgroup,
 # tile depth): the fastest setting of the autotuner on this workload
-DEFAULT_TUNING = "3,4,256"
+DEFAULT_TUNING = "5,4,256"
 # the committed hardware-counter summary of the warp-and-score kernel
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_score_image_speckle160_pmc.md")
 KERNEL_SOURCES = ["paper_2504_19930_amd/csrc/score.hip", "paper_2504_19930_amd/csrc/internal.h",

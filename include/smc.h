@@ -191,8 +191,10 @@ smc_status smc_set_frames(smc_ctx *ctx, uint32_t n_extra, const smc_volume *src_
  * 1 x-pairs (uint16, four), 2 2x2 quads (uint32, two), 3 2x2x2 octets
  * (uint64, one), 4 the same octets stored in 4 x 4 voxel tiles of a slice
  * (one 128-byte cache line per tile, so a rotated footprint touches fewer
- * lines); packed layouts cost 2, 4 or 8 bytes per source voxel of device
- * memory, prepared on the stream.  particles_per_group: particles
+ * lines), 5 the octet cell stored ready for the x-interpolations (four
+ * starts and four steps times 256 in half precision, 16 bytes, one gather
+ * and fewer instructions per sample); packed layouts cost 2, 4, 8 or 16
+ * bytes per source voxel of device memory, prepared on the stream.  particles_per_group: particles
  * sharing one pass over a target column, 4, 8 or 16.  tile_depth: target
  * slices per tile, 1 .. 256 (a tile is 32 x 8 x tile_depth voxels; shallower
  * tiles cull more exactly -- a tile whose image cannot reach the source, or
@@ -200,7 +202,8 @@ smc_status smc_set_frames(smc_ctx *ctx, uint32_t n_extra, const smc_volume *src_
  * more partial sums).  A negative value keeps the current setting.  Defaults
  * come from measurements on MI355X.  A packed layout addresses its source
  * with 32-bit offsets: SMC_EINVAL if the packed source reaches 4 GiB or one
- * packed slice 16 MiB (smc_init then starts from layout 0 instead). */
+ * packed slice 16 MiB.  smc_init starts from layout 5, else 3 if 5 does
+ * not fit, else 0. */
 smc_status smc_set_tuning(smc_ctx *ctx, int32_t layout, int32_t particles_per_group, int32_t tile_depth);
 smc_status smc_get_tuning(smc_ctx *ctx, int32_t *layout, int32_t *particles_per_group, int32_t *tile_depth);
 

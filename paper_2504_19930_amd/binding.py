@@ -258,7 +258,7 @@ def smc_profile_read(ctx) -> dict:
     return dict(score_ms=sm.value, score_launches=sn.value, filter_ms=fm.value, filter_launches=fn.value)
 
 
-LAYOUTS = {"raw": 0, "pairx": 1, "quadxy": 2, "oct": 3, "octtile": 4}
+LAYOUTS = {"raw": 0, "pairx": 1, "quadxy": 2, "oct": 3, "octtile": 4, "lerp": 5}
 
 
 def smc_exhaustive(ctx, lo, step, count, want_scores=False) -> dict:

@@ -27,7 +27,7 @@ thread_local std::string g_err;
 
 // Launch defaults (see smc_set_tuning).
 // (measured on MI355X: packed octets, 4 particles per workgroup; see smc_autotune)
-constexpr int kDefaultLayout = kLayoutOct;
+constexpr int kDefaultLayout = kLayoutLerp;
 constexpr int kDefaultPT = 4;
 constexpr int kDefaultZChunk = 32;
 
@@ -262,7 +262,10 @@ smc_status prepare_layout(smc_ctx *c, int layout) {
     if ((st = c->alloc((uint8_t **)&c->packed[layout], packed_bytes(layout, c->sn))) != SMC_OK) return st;
     uint64_t sent = 0;
     bool ok = false;
-    if (c->src_fov) {
+    if (c->src_fov && layout == kLayoutLerp) {
+        sent = kLerpSentinel;
+        ok = true;
+    } else if (c->src_fov) {
         const int n_cand = layout == kLayoutPairX ? 0 : 64;
         const size_t n_counts = layout == kLayoutPairX ? 65536 : 64;
         std::vector<uint64_t> cand(64);
@@ -420,7 +423,7 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
         }
     }
 
-    if (!layout_fits(c->layout, c->sn)) c->layout = kLayoutRaw;
+    if (!layout_fits(c->layout, c->sn)) c->layout = layout_fits(kLayoutOct, c->sn) ? kLayoutOct : kLayoutRaw;
     if ((st = prepare_layout(c, c->layout)) != SMC_OK) return bail(st);
 
     if (c->mode == kModeMask) {
@@ -895,7 +898,8 @@ smc_status smc_autotune(smc_ctx *c, uint32_t reps, double *best_ms) {
     const uint32_t np = c->f.n + 1;
     if ((st = ensure_eval(c, np)) != SMC_OK) return c->mark(st);
     std::vector<int> layouts = {kLayoutRaw};
-    if (c->mode == kModeImageTrilinear) layouts = {kLayoutRaw, kLayoutPairX, kLayoutQuadXY, kLayoutOct, kLayoutOctTile};
+    if (c->mode == kModeImageTrilinear)
+        layouts = {kLayoutRaw, kLayoutPairX, kLayoutQuadXY, kLayoutOct, kLayoutOctTile, kLayoutLerp};
     const int depths_img[] = {32, 256}, depths_mask[] = {16, 32, 256};
     const int *depths = c->mode == kModeMask ? depths_mask : depths_img;
     const int nd = c->mode == kModeMask ? 3 : 2;

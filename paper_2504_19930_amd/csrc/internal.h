@@ -13,9 +13,20 @@ namespace smc {
 enum ScoreMode : int { kModeMask = 0, kModeImageTrilinear = 1, kModeImageNearest = 2 };
 
 // Source layouts for trilinear sampling (see score.hip): bytes per voxel
-// 1, 2, 4, 8; eight, four, two or one gathers per sample.
-enum SourceLayout : int { kLayoutRaw = 0, kLayoutPairX = 1, kLayoutQuadXY = 2, kLayoutOct = 3, kLayoutOctTile = 4 };
-constexpr int kLayouts = 5;
+// 1, 2, 4, 8, 8, 16; eight, four, two or one gathers per sample.
+enum SourceLayout : int {
+    kLayoutRaw = 0,
+    kLayoutPairX = 1,
+    kLayoutQuadXY = 2,
+    kLayoutOct = 3,
+    kLayoutOctTile = 4,
+    kLayoutLerp = 5
+};
+constexpr int kLayouts = 6;
+// The lerp layout marks elements that touch a voxel outside the source FOV
+// with a pair of half-precision NaNs in the first word; no valid element
+// holds a NaN, so this sentinel always exists.
+constexpr uint32_t kLerpSentinel = 0x7E007E00u;
 
 struct ScoreLaunch {
     int mode;

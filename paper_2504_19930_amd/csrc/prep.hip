@@ -72,7 +72,8 @@ __global__ __launch_bounds__(256) void k_volume_sums(const uint8_t *vol, const u
 // with corners past the last voxel repeating it (see score.hip).  The
 // element of voxel q and its FOV validity (all voxels it covers inside):
 //   pairx  (v[x], v[x+1]) of one row;  quadxy  the 2x2 of one slice;
-//   oct    the 2x2x2 of the trilinear cell.
+//   oct    the 2x2x2 of the trilinear cell (lerp stores the same cell ready
+//          for the x-lerps).
 // A trilinear sample is inside the FOV iff every element it reads is, so an
 // invalid element may hold a sentinel value that no valid element takes.
 struct Elem {
@@ -121,6 +122,29 @@ __global__ void k_pack_source(const uint8_t *vol, const uint8_t *fov, int32_t nx
             ((uint16_t *)out)[q] = (uint16_t)v;
         } else if (layout == kLayoutQuadXY) {
             ((uint32_t *)out)[q] = (uint32_t)v;
+        } else if (layout == kLayoutLerp) {
+            // the four x-lerp starts a = v(x, .) and steps d = v(x + 1, .) - v(x, .)
+            // of the rows (y, z), (y + 1, z), (y, z + 1), (y + 1, z + 1), each times
+            // 256 in half precision (exact: |256 v| <= 65280 with at most eight
+            // significant bits); elements outside the FOV carry the NaN sentinel
+            uint32_t w[4];
+            if (e.valid) {
+                uint32_t h[8];
+                for (int r = 0; r < 4; ++r) {
+                    const int lo = (int)((e.value >> (16 * r)) & 0xFFu), hi = (int)((e.value >> (16 * r + 8)) & 0xFFu);
+                    const _Float16 a = (_Float16)(256.0f * (float)lo), d = (_Float16)(256.0f * (float)(hi - lo));
+                    h[r] = __builtin_bit_cast(uint16_t, a);
+                    h[4 + r] = __builtin_bit_cast(uint16_t, d);
+                }
+                w[0] = h[0] | (h[1] << 16);
+                w[1] = h[2] | (h[3] << 16);
+                w[2] = h[4] | (h[5] << 16);
+                w[3] = h[6] | (h[7] << 16);
+            } else {
+                w[0] = kLerpSentinel;
+                w[1] = w[2] = w[3] = 0u;
+            }
+            ((uint4 *)out)[q] = make_uint4(w[0], w[1], w[2], w[3]);
         } else {
             int64_t o = q;
             if (layout == kLayoutOctTile) {
@@ -198,6 +222,7 @@ size_t packed_bytes_per_voxel(int layout) {
     case kLayoutPairX: return 2;
     case kLayoutQuadXY: return 4;
     case kLayoutOct: case kLayoutOctTile: return 8;
+    case kLayoutLerp: return 16;
     default: return 1;
     }
 }

@@ -215,6 +215,23 @@ __device__ __forceinline__ uint32_t floor_u32(float x) {
     return (uint32_t)r;
 }
 
+// a * b + c on the low 24 bits of a and b, as one instruction (the compiler
+// otherwise forms two multiplies and a three-way add); b is uniform across
+// the wave (a stride) and is passed as a scalar operand.
+__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
+// floor(x + 0.5) as an integer in one instruction (x + 0.5 is exact for the
+// non-negative values below 2^22 it is given).
+__device__ __forceinline__ uint32_t round_half_up_u32(float x) {
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return (uint32_t)r;
+}
+
 // ---------------------------------------------------------------- masks
 
 // Source byte: bit 0 = inside the source FOV, bit 1 = mask on (and in FOV).
@@ -321,6 +338,7 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
 
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Packed corners through a buffer resource with 32-bit byte offsets:
 // off = the base element, dy / dz the byte steps to the element one row /
@@ -397,6 +415,20 @@ __device__ __forceinline__ void x_lerps(uint32_t lo, uint32_t hi, float f, float
     x11 = fmaf(f, (float)d1.y, (float)v1.y);
 }
 
+// The four x-lerps from a lerp-layout element: w0, w1 hold the starts a and
+// w2, w3 the steps d (times 256, in half precision) of the rows (y, z),
+// (y + 1, z), (y, z + 1), (y + 1, z + 1).  One mixed-precision FMA per lerp
+// forms f * 256 d + 256 a in FP32 with one rounding; scaling by a power of
+// two commutes with the rounding, so this is exactly 256 fma(f, d, a).
+__device__ __forceinline__ void x_lerps_scaled(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, float f,
+                                               float &x00, float &x10, float &x01, float &x11) {
+    const half2v a0 = as_half2(w0), a1 = as_half2(w1), d0 = as_half2(w2), d1 = as_half2(w3);
+    x00 = fmaf(f, (float)d0.x, (float)a0.x);
+    x10 = fmaf(f, (float)d0.y, (float)a0.y);
+    x01 = fmaf(f, (float)d1.x, (float)a1.x);
+    x11 = fmaf(f, (float)d1.y, (float)a1.y);
+}
+
 // Raw packed corner words (quads and octets): lo = slice z, hi = slice z + 1.
 template <int LAYOUT>
 __device__ __forceinline__ void corner_words(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t dz, uint32_t &lo,
@@ -421,6 +453,8 @@ __device__ __forceinline__ void corner_words(__amdgpu_buffer_rsrc_t rs, uint32_t
 //   pairx  uint16 (v[x], v[x+1]), four gathers
 //   quadxy uint32 (v[x,y], v[x+1,y], v[x,y+1], v[x+1,y+1]), two gathers
 //   oct    uint64 (quad of slice z, quad of slice z+1), one gather
+//   lerp   the oct cell as four x-lerp starts and steps times 256 in half
+//          precision (16 bytes), one gather; see x_lerps_scaled
 template <int LAYOUT>
 __device__ __forceinline__ void corners(const void *src, uint32_t base, uint32_t dx, uint32_t dy, uint32_t dz,
                                         float v[8], uint64_t sentinel, bool &sent_ok) {
@@ -513,7 +547,10 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
         const float ex = (float)(a.sn0 - 1), ey = (float)(a.sn1 - 1), ez = (float)(a.sn2 - 1);
         const bool tfov = a.tgt_fov != nullptr;
         constexpr uint32_t kElemShift =
-            LAYOUT == kLayoutOct || LAYOUT == kLayoutOctTile ? 3u : (LAYOUT == kLayoutQuadXY ? 2u : 1u);
+            LAYOUT == kLayoutLerp ? 4u
+                                  : (LAYOUT == kLayoutOct || LAYOUT == kLayoutOctTile
+                                         ? 3u
+                                         : (LAYOUT == kLayoutQuadXY ? 2u : 1u));
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(a.src_packed), (short)0, (int)a.src_bytes,
                                               kBufferWord3);
@@ -584,7 +621,7 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                         off[p] = o + __umul24(iy, a.ysb) + __umul24(iz, a.zsb);
                         if (SOK) vidx[p] = ix + sn0 * iy + sn01 * iz;
                     } else {
-                        off[p] = __umul24(iz, a.zsb) + __umul24(iy, a.ysb) + (ix << kElemShift);
+                        off[p] = mad_u24(iz, a.zsb, mad_u24(iy, a.ysb, ix << kElemShift));
                         if (SOK) vidx[p] = off[p] >> kElemShift;
                     }
                     if (LAYOUT == kLayoutPairX) ddy[p] = iy < (uint32_t)(a.sn1 - 1) ? a.ysb : 0u;
@@ -593,15 +630,23 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                 }
                 uint32_t okv[PT];
                 float v[PT][8];
-                uint32_t wlo[PT], whi[PT];
+                uint32_t wlo[PT], whi[PT], wd0[PT], wd1[PT];
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
                     bool sent_ok;
-                    if constexpr (LAYOUT == kLayoutPairX)
+                    if constexpr (LAYOUT == kLayoutPairX) {
                         corners_buf<LAYOUT>(rs, off[p], ddy[p], ddz[p], v[p], a.sentinel, sent_ok);
-                    else
+                    } else if constexpr (LAYOUT == kLayoutLerp) {
+                        const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rs, off[p], 0, 0);
+                        wlo[p] = w.x;
+                        whi[p] = w.y;
+                        wd0[p] = w.z;
+                        wd1[p] = w.w;
+                        sent_ok = w.x != kLerpSentinel;
+                    } else {
                         corner_words<LAYOUT>(rs, off[p], LAYOUT == kLayoutQuadXY ? ddz[p] : 0u, wlo[p], whi[p],
                                              a.sentinel, sent_ok);
+                    }
                     okv[p] = SOK ? __builtin_amdgcn_raw_buffer_load_b8(rs_ok, vidx[p], 0, 0)
                                  : (VMODE == 2 ? (sent_ok ? 1u : 0u) : 1u);
                 }
@@ -613,24 +658,28 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                         x10 = fmaf(fxa[p], v[p][3] - v[p][2], v[p][2]);
                         x01 = fmaf(fxa[p], v[p][5] - v[p][4], v[p][4]);
                         x11 = fmaf(fxa[p], v[p][7] - v[p][6], v[p][6]);
+                    } else if constexpr (LAYOUT == kLayoutLerp) {
+                        x_lerps_scaled(wlo[p], whi[p], wd0[p], wd1[p], fxa[p], x00, x10, x01, x11);
                     } else {
                         x_lerps(wlo[p], whi[p], fxa[p], x00, x10, x01, x11);
                     }
                     const float y0 = fmaf(fya[p], x10 - x00, x00);
                     const float y1 = fmaf(fya[p], x11 - x01, x01);
                     const float sv = fmaf(fza[p], y1 - y0, y0);
-                    // s * 256 is exact, so one fused step equals the multiply-add
-                    const uint32_t sfx0 = (uint32_t)fmaf(sv, 256.0f, 0.5f);
+                    // s * 256 is exact, so one fused step equals the multiply-add;
+                    // the lerp layout's samples already carry the factor 256
+                    const uint32_t sfx0 =
+                        LAYOUT == kLayoutLerp ? round_half_up_u32(sv) : (uint32_t)fmaf(sv, 256.0f, 0.5f);
                     const bool valid = in[p] & (okv[p] != 0u);
-                    const uint32_t sfx = valid ? sfx0 : 0u;
                     if constexpr (HIST) {
                         if (valid) atomicAdd(&lhist[p][(sfx0 >> 11) * kMiBins + (tv >> 3)], 1u);
-                    } else {
-                        nt[p] += valid ? nt1 : 0u;
-                        acc[p].s += sfx;
-                        acc[p].ss += (unsigned long long)sfx * sfx;
-                        acc[p].tt += valid ? tv2 : 0u;
-                        acc[p].st += __umul24(sfx, tv);  // s_fx < 2^16, t < 2^8
+                    } else if (valid) {
+                        // under the lane mask: no selects on the five updates
+                        nt[p] += nt1;
+                        acc[p].s += sfx0;
+                        acc[p].ss += (unsigned long long)sfx0 * sfx0;
+                        acc[p].tt += tv2;
+                        acc[p].st += __umul24(sfx0, tv);  // s_fx < 2^16, t < 2^8
                     }
                 }
             } else if (TRI) {
@@ -783,7 +832,9 @@ __global__ __launch_bounds__(kThreads) void k_score_mask(const KArgs a) {
 // spilling: ask for the seven waves per SIMD that allows.
 template <int PT, int LAYOUT, int VMODE, int ACC>
 constexpr int kImageWaves =
-    PT == 4 && (LAYOUT == kLayoutOct || LAYOUT == kLayoutOctTile) && VMODE != 1 && ACC == 0 ? 7 : 1;
+    PT == 4 && (LAYOUT == kLayoutOct || LAYOUT == kLayoutOctTile) && VMODE != 1 && ACC == 0
+        ? 7
+        : (PT == 4 && LAYOUT == kLayoutLerp && VMODE != 1 && ACC == 0 ? 6 : 1);
 
 template <int PT, int LAYOUT, bool TRI, int VMODE, int ACC = 0>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kImageWaves<PT, LAYOUT, VMODE, ACC>)))
@@ -913,6 +964,7 @@ ScoreKernel pick_tri_layout(int layout, int vmode) {
     case kLayoutQuadXY: return pick_tri<PT, kLayoutQuadXY, ACC>(vmode);
     case kLayoutOct: return pick_tri<PT, kLayoutOct, ACC>(vmode);
     case kLayoutOctTile: return pick_tri<PT, kLayoutOctTile, ACC>(vmode);
+    case kLayoutLerp: return pick_tri<PT, kLayoutLerp, ACC>(vmode);
     default: return pick_tri<PT, kLayoutRaw, ACC>(vmode);
     }
 }
@@ -973,6 +1025,7 @@ ScoreKernel pick_batch(int mode, int layout, int vmode) {
     case kLayoutQuadXY: return pick_batch_image<PT, kLayoutQuadXY>(vmode);
     case kLayoutOct: return pick_batch_image<PT, kLayoutOct>(vmode);
     case kLayoutOctTile: return pick_batch_image<PT, kLayoutOctTile>(vmode);
+    case kLayoutLerp: return pick_batch_image<PT, kLayoutLerp>(vmode);
     default: return pick_batch_image<PT, kLayoutRaw>(vmode);
     }
 }

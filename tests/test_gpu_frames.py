@@ -67,7 +67,7 @@ def test_pooled_image_sums_bit_exact_every_layout(smc, orc):
     r.set_frames([dict(src=dev(f["src"]), tgt=dev(f["tgt"]), src_fov=dev(f["src_fov"])) for f in fr[1:]])
     x = np.vstack([np.zeros(6), _states(40, 20, 3, 8)])
     want = orc.Frames([(orc.Volume(f["src"], fov=f["src_fov"]), orc.Volume(f["tgt"])) for f in fr]).sums(prm, x)
-    for layout in ("raw", "quadxy", "oct", "octtile"):
+    for layout in ("raw", "quadxy", "oct", "octtile", "lerp"):
         r.tune(layout, 4, 32)
         assert np.array_equal(r.evaluate(x), want), layout
 

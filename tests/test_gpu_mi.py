@@ -43,7 +43,7 @@ def test_mi_scores_bit_exact_every_layout(smc, orc, with_fov):
     src = orc.Volume(pair["src"], fov=pair["src_fov"] if with_fov else None)
     want = orc.Problem(src, orc.Volume(pair["tgt"])).score(prm, x)
     assert np.isneginf(want[-1])  # below the minimum overlap
-    for layout in ("raw", "pairx", "quadxy", "oct", "octtile"):
+    for layout in ("raw", "pairx", "quadxy", "oct", "octtile", "lerp"):
         for pt in (4, 8):
             r.tune(layout, pt, 32)
             got = r.scores(x)

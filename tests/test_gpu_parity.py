@@ -305,7 +305,7 @@ def test_tuning_invariance(smc, orc):
     r = _reg(smc, pair, prm, src_fov=pair["src_fov"])
     x = np.vstack([np.zeros(6), _random_states(40, 20, 3, 8)])
     want = _oracle_sums(orc, orc.Volume(pair["src"], fov=pair["src_fov"]), orc.Volume(pair["tgt"]), x, "trilinear")
-    for layout in ("raw", "pairx", "quadxy", "oct", "octtile"):
+    for layout in ("raw", "pairx", "quadxy", "oct", "octtile", "lerp"):
         for pt in (4, 8, 16):
             for depth in (7, 32, 256):
                 r.tune(layout, pt, depth)
@@ -317,7 +317,7 @@ def test_tuning_invariance(smc, orc):
                src_fov=np.ascontiguousarray(pair["src_fov"][:29, :34, :35]))
     rc = _reg(smc, cut, prm, src_fov=cut["src_fov"])
     wc = _oracle_sums(orc, orc.Volume(cut["src"], fov=cut["src_fov"]), orc.Volume(cut["tgt"]), x, "trilinear")
-    for layout in ("raw", "oct", "octtile"):
+    for layout in ("raw", "oct", "octtile", "lerp"):
         rc.tune(layout, 4, 32)
         assert np.array_equal(rc.evaluate(x), wc), layout
     mpair = synth.shell_pair(seed=3, side=40)
@@ -438,7 +438,7 @@ def test_autotune_keeps_results(smc, orc):
     prm = config.default_params("ncc", 64, 2, 20.0, 4.0)
     r = _reg(smc, pair, prm, src_fov=pair["src_fov"])
     t = r.autotune(reps=2)
-    assert t["layout"] in (0, 1, 2, 3, 4) and t["particles_per_group"] in (4, 8) and t["ms"] > 0
+    assert t["layout"] in (0, 1, 2, 3, 4, 5) and t["particles_per_group"] in (4, 8) and t["ms"] > 0
     x = _random_states(20, 20, 4, 23)
     want = _oracle_sums(orc, orc.Volume(pair["src"], fov=pair["src_fov"]), orc.Volume(pair["tgt"]), x, "trilinear")
     assert np.array_equal(r.evaluate(x), want)
@@ -471,6 +471,6 @@ def test_fov_sentinel_and_fallback_exact(smc, orc):
     x[:, 1] = 0.0  # stay within the two slices
     x[:, 5] = 0.0
     want = _oracle_sums(orc, orc.Volume(src, fov=fov), orc.Volume(tgt), x, "trilinear")
-    for layout in ("pairx", "quadxy", "oct", "octtile", "raw"):
+    for layout in ("pairx", "quadxy", "oct", "octtile", "lerp", "raw"):
         r.tune(layout, 4, 32)
         assert np.array_equal(r.evaluate(x), want), layout
