@@ -208,11 +208,14 @@ smc_status smc_set_tuning(smc_ctx *ctx, int32_t layout, int32_t particles_per_gr
 smc_status smc_get_tuning(smc_ctx *ctx, int32_t *layout, int32_t *particles_per_group, int32_t *tile_depth);
 
 /* Autotuner: time every candidate tuning (layouts for trilinear images;
- * particles per group 4 / 8; tile depths) on this context's own volumes and
- * current particles with HIP events (reps launches each, on a scratch sum
- * buffer), and apply the fastest.  Results are cached per problem shape for
- * the life of the process.  best_ms (may be NULL) receives the fastest
- * launch time.  Syncs. */
+ * particles per group 4 / 8; tile depths) on this context's own volumes with
+ * HIP events (reps launches each, on a scratch sum buffer) over two particle
+ * sets -- the current particles (after smc_init, the prior) and a cloud
+ * concentrated within 5 % of the limits around x0, standing in for the
+ * iterations after the first -- and apply the tuning with the least time per
+ * registration (the first set once, the second n_iters - 1 times).  Results
+ * are cached per problem shape for the life of the process.  best_ms (may be
+ * NULL) receives that cost per launch.  Syncs. */
 smc_status smc_autotune(smc_ctx *ctx, uint32_t reps, double *best_ms);
 
 /* Kernel timing.  With enable != 0 every warp-and-score launch and every

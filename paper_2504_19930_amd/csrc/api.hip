@@ -897,6 +897,25 @@ smc_status smc_autotune(smc_ctx *c, uint32_t reps, double *best_ms) {
     }
     const uint32_t np = c->f.n + 1;
     if ((st = ensure_eval(c, np)) != SMC_OK) return c->mark(st);
+    // Two particle sets are timed: the prior (the context's current set,
+    // spread over the whole limits box) and a concentrated cloud like the one
+    // the filter evaluates after its first iterations (x0 +- 5 % of the
+    // limits, a low-discrepancy fill), weighted by how often each occurs in a
+    // registration: the cloud's locality decides which layout gathers best.
+    {
+        std::vector<double> xs(6ull * np);
+        for (uint32_t i = 0; i < np; ++i)
+            for (int d = 0; d < 6; ++d) {
+                const double alpha = sqrt((double)(2 + 3 * d)) - floor(sqrt((double)(2 + 3 * d)));
+                const double h = 0.5 + (double)i * alpha;
+                xs[6ull * i + d] = c->p.x0[d] + 0.05 * c->p.limit[d] * (2.0 * (h - floor(h)) - 1.0);
+            }
+        if (hipMemcpyAsync(c->x_eval, xs.data(), 48ull * np, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            launch_words(c->x_eval, np, c->f.geom, c->f.nearest, c->w_eval, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return c->mark(fail(SMC_EDEVICE, "autotune particle set failed"));
+    }
+    const double w_conc = c->f.n_iters > 1 ? (double)(c->f.n_iters - 1) : 0.0;
     std::vector<int> layouts = {kLayoutRaw};
     if (c->mode == kModeImageTrilinear)
         layouts = {kLayoutRaw, kLayoutPairX, kLayoutQuadXY, kLayoutOct, kLayoutOctTile, kLayoutLerp};
@@ -912,19 +931,23 @@ smc_status smc_autotune(smc_ctx *c, uint32_t reps, double *best_ms) {
         for (int pt : {4, 8})
             for (int q = 0; q < nd && result == SMC_OK && layout_fits(lay, c->sn); ++q) {
                 if ((result = smc_set_tuning(c, lay, pt, depths[q])) != SMC_OK) break;
-                ScoreLaunch L = c->score_launch(c->f.words, c->s_eval, 0, np, true);
-                if (c->p.score == SMC_SCORE_MI) L.hist = c->hist_eval;
-                double tot = 0.0;
-                for (uint32_t r = 0; r <= reps && result == SMC_OK; ++r) {
-                    float ms = 0.0f;
-                    if (launch_fill_u64(c->s_eval, 6ull * np, c->stream) != hipSuccess ||
-                        hipEventRecord(e0, c->stream) != hipSuccess || launch_score(L, c->stream) != hipSuccess ||
-                        hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-                        result = fail(SMC_EDEVICE, "autotune launch failed");
-                    if (r > 0) tot += ms;  // the first launch warms caches
+                double cost = 0.0;
+                for (int set = 0; set < 2 && result == SMC_OK; ++set) {
+                    ScoreLaunch L = c->score_launch(set == 0 ? c->f.words : c->w_eval, c->s_eval, 0, np, true);
+                    if (c->p.score == SMC_SCORE_MI) L.hist = c->hist_eval;
+                    double tot = 0.0;
+                    for (uint32_t r = 0; r <= reps && result == SMC_OK; ++r) {
+                        float ms = 0.0f;
+                        if (launch_fill_u64(c->s_eval, 6ull * np, c->stream) != hipSuccess ||
+                            hipEventRecord(e0, c->stream) != hipSuccess || launch_score(L, c->stream) != hipSuccess ||
+                            hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                            result = fail(SMC_EDEVICE, "autotune launch failed");
+                        if (r > 0) tot += ms;  // the first launch warms caches
+                    }
+                    cost += (set == 0 ? 1.0 : w_conc) * tot / reps;
                 }
-                const double avg = tot / reps;
+                const double avg = cost / (1.0 + w_conc);  // per launch over a registration
                 if (avg < best.ms) best = TuneVal{lay, pt, depths[q], avg};
             }
     (void)hipEventDestroy(e0);
@@ -1082,7 +1105,10 @@ int device_cus() {
 // volume) and the lists stay balanced whatever the mix of pairs.
 smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode, int vmode) {
     const uint32_t n = (uint32_t)C.members.size();
-    if (n == 0) return SMC_OK;
+    if (n == 0) {
+        C.plan = BatchPlan{};  // an empty class launches nothing (also after a re-plan)
+        return SMC_OK;
+    }
     const size_t ab = score_args_bytes();
     std::vector<uint8_t> args(ab * n);
     std::vector<uint32_t> offs(n + 1, 0), kmax(n);
@@ -1090,9 +1116,13 @@ smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode, int vmode) {
     int pt = 8, layout = kLayoutRaw;
     for (uint32_t q = 0; q < n; ++q) {
         smc_ctx *c = b->pairs[C.members[q]];
-        const ScoreLaunch L = c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true);
-        pt = L.pt;
-        layout = L.layout;
+        ScoreLaunch L = c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true);
+        if (q == 0) {
+            pt = L.pt;
+            layout = L.layout;
+        } else if (L.pt != pt || L.layout != layout) {
+            return fail(SMC_EINVAL, "batch class mixes tunings (pair %u)", C.members[q]);
+        }
         score_args(L, args.data() + ab * q);
         const uint32_t items = score_items(L);
         offs[q + 1] = offs[q] + items;
@@ -1120,7 +1150,8 @@ smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode, int vmode) {
     }
     smc_status st;
     if ((st = b->alloc((uint8_t **)&C.args, args.size())) != SMC_OK || (st = b->alloc(&C.offs, n + 1)) != SMC_OK ||
-        (st = b->alloc(&C.kmax, n)) != SMC_OK || (st = b->alloc(&C.lists, flat.size())) != SMC_OK)
+        (st = b->alloc(&C.kmax, n)) != SMC_OK || (st = b->alloc(&C.lists, flat.size())) != SMC_OK ||
+        (st = b->alloc(&C.plan.counters, 8ull * std::max(1u, b->kmax_all))) != SMC_OK)
         return st;
     HIP_TRY(hipMemcpy(C.args, args.data(), args.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(C.offs, offs.data(), 4 * (n + 1), hipMemcpyHostToDevice));
@@ -1144,6 +1175,21 @@ smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode, int vmode) {
 // Split the image pairs by source FOV validity mode (one kernel variant per
 // class keeps each variant's register budget) and plan every class.
 smc_status plan_all(smc_batch *b) {
+    // one kernel variant serves a class: every image pair takes the first
+    // image pair's layout and particles per group, every mask pair the first
+    // mask pair's particles per group (before the FOV modes are read, since a
+    // layout decides whether a pair has an in-band FOV sentinel)
+    for (int q = 0; q < 2; ++q) {
+        const std::vector<uint32_t> &members = q == 0 ? b->cls[0].members : b->images;
+        if (members.empty()) continue;
+        const smc_ctx *c0 = b->pairs[members[0]];
+        for (uint32_t i : members) {
+            smc_ctx *c = b->pairs[i];
+            if ((q == 1 && c->layout != c0->layout) || c->pt != c0->pt)
+                if (smc_set_tuning(c, q == 1 ? c0->layout : -1, c0->pt, -1) != SMC_OK)
+                    return fail(SMC_EINVAL, "pair %u cannot take the tuning of pair %u", i, members[0]);
+        }
+    }
     for (int q = 1; q < 4; ++q) b->cls[q].members.clear();
     for (uint32_t i : b->images) {
         smc_ctx *c = b->pairs[i];
@@ -1161,6 +1207,11 @@ smc_status plan_all(smc_batch *b) {
 smc_status record_run(smc_batch *b) {
     HIP_TRY(launch_init_batch(b->states_dev, (uint32_t)b->pairs.size(), b->max_threads, b->stream));
     for (smc_ctx *c : b->pairs) HIP_TRY(launch_fill_u64(c->f.sums, 6ull * (c->f.n + 1), b->stream));
+    // the item queues start empty on every run (a fill kernel, so graph replays clear them too)
+    for (int q = 0; q < 4; ++q)
+        if (b->cls[q].plan.n_pairs)
+            HIP_TRY(launch_fill_u64((unsigned long long *)b->cls[q].plan.counters, 4ull * std::max(1u, b->kmax_all),
+                                    b->stream));
     for (uint32_t k = 1; k <= b->kmax_all; ++k) {
         for (int q = 0; q < 4; ++q) HIP_TRY(launch_batch_score(b->cls[q].plan, k, b->stream));
         for (uint32_t i : b->singles) {

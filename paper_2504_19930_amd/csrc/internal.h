@@ -82,6 +82,9 @@ struct BatchPlan {
     uint32_t list_off[9];
     uint32_t n_pairs;
     uint32_t grid;            // persistent workgroups
+    // item queues: 8 counters (one per XCD list) per iteration, zero before
+    // the run; iteration k uses counters[8 (k - 1) .. 8 k)
+    uint32_t *counters;
 };
 size_t score_args_bytes();
 uint32_t score_items(const ScoreLaunch &L);

@@ -850,7 +850,11 @@ void k_score_image(const KArgs a) {
 // pair d (offs[d] <= g < offs[d + 1]) is particle group (g - offs[d]) mod
 // ngroups(d) of tile (g - offs[d]) / ngroups(d).  Work lists are partitioned by
 // XCD: workgroup b serves list b % 8 (the dispatcher hands workgroups to the
-// eight XCDs round robin), so each pair's items stay on one XCD's L2.
+// eight XCDs round robin), so each pair's items stay on one XCD's L2.  The
+// workgroups of an XCD take the items of its list in order from a shared
+// counter, so the items in flight stay a narrow window of neighbouring tiles
+// (a fixed stride per workgroup lets fast and slow workgroups drift apart
+// until the window spans many pairs and the L2 hit rate collapses).
 struct BatchArgs {
     const KArgs *pairs;
     const uint32_t *offs;      // n_pairs + 1 item offsets
@@ -859,6 +863,7 @@ struct BatchArgs {
     uint32_t list_off[9];      // list x = lists[list_off[x] .. list_off[x + 1])
     uint32_t n_pairs;
     uint32_t k;                // iteration being scored (pairs with kmax < k are done)
+    uint32_t *counters;        // 8 item counters of this launch, zero at launch
 };
 
 __device__ __forceinline__ uint32_t pair_of(const uint32_t *offs_g, uint32_t n, uint32_t g) {
@@ -873,23 +878,37 @@ __device__ __forceinline__ uint32_t pair_of(const uint32_t *offs_g, uint32_t n, 
 }
 
 template <int PT, int MODE, int LAYOUT, int VMODE>
-__global__ __launch_bounds__(kThreads) void k_batch_score(const BatchArgs b) {
-    const uint32_t x = blockIdx.x % 8, per = gridDim.x / 8 + ((blockIdx.x % 8) < gridDim.x % 8 ? 1u : 0u);
-    const uint32_t begin = b.list_off[x], end = b.list_off[x + 1];
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(MODE == kModeMask ? 1 : kImageWaves<PT, LAYOUT, VMODE, 0>)))
+void k_batch_score(const BatchArgs b) {
     const auto *lists = as_const(b.lists);
     const auto *kmax = as_const(b.kmax);
     const auto *pairs = as_const(b.pairs);
-    for (uint32_t q = begin + blockIdx.x / 8; q < end; q += per) {
-        const uint32_t g = lists[q];
-        const uint32_t d = pair_of(b.offs, b.n_pairs, g);
-        if (kmax[d] < b.k) continue;
-        const KArgs a = pairs[d];
-        const uint32_t local = g - b.offs[d];
-        const uint32_t ng = (a.np + PT - 1) / PT;
-        const uint32_t bx = local / ng, by = local - bx * ng;
-        if (MODE == kModeMask) mask_body<PT>(a, bx, by);
-        else image_body<PT, LAYOUT, true, VMODE>(a, bx, by);
-        __syncthreads();
+    __shared__ uint32_t next_item;
+    // the XCD's own list first, then the other lists' remaining items (the
+    // tails hold the smallest pairs), so no XCD idles while another has work;
+    // every workgroup leaves once all eight counters have passed their ends
+    for (uint32_t s = 0; s < 8; ++s) {
+        const uint32_t x = (blockIdx.x + s) % 8;
+        const uint32_t begin = b.list_off[x], n_items = b.list_off[x + 1] - begin;
+        for (;;) {
+            if (threadIdx.x == 0) next_item = atomicAdd(b.counters + x, 1u);
+            __syncthreads();
+            const uint32_t r = next_item;
+            if (r >= n_items) break;
+            const uint32_t g = lists[begin + r];
+            const uint32_t d = pair_of(b.offs, b.n_pairs, g);
+            if (kmax[d] >= b.k) {  // pairs with fewer iterations are done
+                const KArgs a = pairs[d];
+                const uint32_t local = g - b.offs[d];
+                const uint32_t ng = (a.np + PT - 1) / PT;
+                const uint32_t bx = local / ng, by = local - bx * ng;
+                if (MODE == kModeMask) mask_body<PT>(a, bx, by);
+                else image_body<PT, LAYOUT, true, VMODE>(a, bx, by);
+            }
+            __syncthreads();  // next_item is read by all before thread 0 takes the next
+        }
+        __syncthreads();  // the same before the next list's first take
     }
 }
 
@@ -1046,6 +1065,7 @@ hipError_t launch_batch_score(const BatchPlan &P, uint32_t k, hipStream_t s) {
     for (int x = 0; x < 9; ++x) b.list_off[x] = P.list_off[x];
     b.n_pairs = P.n_pairs;
     b.k = k;
+    b.counters = P.counters + 8ull * (k - 1);
     typedef void (*BK)(const BatchArgs);
     BK kern = reinterpret_cast<BK>(const_cast<void *>(batch_kernel(P)));
     hipLaunchKernelGGL(kern, dim3(P.grid), dim3(kThreads), 0, s, b);
