@@ -74,7 +74,7 @@ typedef enum { SMC_INTERP_NEAREST = 0, SMC_INTERP_TRILINEAR = 1 } smc_interp;
 typedef enum { SMC_ROTATION_BOX = 0, SMC_ROTATION_WIDE = 1 } smc_rotation;
 
 typedef struct {
-    int32_t nx, ny, nz;      /* voxels, each >= 1 */
+    int32_t nx, ny, nz;      /* voxels, each 1 .. 65535; nx*ny < 2^24, nx*ny*nz < 2^31 */
     double sx, sy, sz;       /* spacing in mm, > 0 */
     const uint8_t *data;     /* device, nz*ny*nx bytes */
     const uint8_t *fov;      /* device or NULL; nonzero = inside the imaged field of view */

@@ -60,6 +60,8 @@ smc_status check_volume(const smc_volume *v, const char *name) {
         return fail(SMC_EINVAL, "%s dimensions %d x %d x %d outside 1..65535", name, v->nx, v->ny, v->nz);
     if ((int64_t)v->nx * v->ny * v->nz >= ((int64_t)1 << 31))
         return fail(SMC_EINVAL, "%s has 2^31 voxels or more", name);
+    if ((int64_t)v->nx * v->ny >= ((int64_t)1 << 24))
+        return fail(SMC_EINVAL, "%s has 2^24 voxels or more per slice", name);
     if (!(v->sx > 0 && v->sy > 0 && v->sz > 0) || !isfinite(v->sx) || !isfinite(v->sy) || !isfinite(v->sz))
         return fail(SMC_EINVAL, "%s spacing must be finite and positive", name);
     return SMC_OK;

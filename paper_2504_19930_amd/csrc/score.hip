@@ -224,6 +224,9 @@ __device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) 
     return r;
 }
 
+// The same with a constant b.
+__device__ __forceinline__ uint32_t mad_u24v(uint32_t a, uint32_t b, uint32_t c) { return __umul24(a, b) + c; }
+
 // floor(x + 0.5) as an integer in one instruction (x + 0.5 is exact for the
 // non-negative values below 2^22 it is given).
 __device__ __forceinline__ uint32_t round_half_up_u32(float x) {
@@ -292,15 +295,20 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
                     const bool in = ((live >> p) & 1u) & (__float_as_uint(ux) < nxb) & (__float_as_uint(uy) < nyb) &
                                     (__float_as_uint(uz) < nzb);
                     msk[p] = in ? keep : 0u;
-                    off[p] = floor_u32(ux) + __umul24(floor_u32(uy), sn0) + floor_u32(uz) * sn01;
+                    // 24-bit multiply-adds: exact inside (offsets below 2^32);
+                    // outside samples form arbitrary offsets, masked below
+                    off[p] = mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, floor_u32(ux)));
                 }
                 uint32_t val[PT];
 #pragma unroll
                 for (int p = 0; p < PT; ++p) val[p] = __builtin_amdgcn_raw_buffer_load_b8(rs, off[p], 0, 0);
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
+                    // v in 0..3 (bit 0 in both FOVs, bit 1 also on); inc = (v & 1) +
+                    // (v >> 1) 2^16 = v + (v >> 1) (2^16 - 2).  Selects rather than a
+                    // branch on the flag, which would pull the load into the branch
                     const uint32_t v = val[p] & msk[p];
-                    const uint32_t inc = (v & 1u) | ((v & 2u) << 15);
+                    const uint32_t inc = mad_u24v(v >> 1, 65534u, v);
                     acc1[p] += inc;
                     acc2[p] += ton ? inc : 0u;
                 }

@@ -67,7 +67,7 @@ def test_bad_params_rejected_before_device_work(smc, bad):
 
 
 @pytest.mark.parametrize("vol", [dict(nx=0), dict(nz=70000), dict(s=0.0), dict(s=float("inf")), dict(data=None),
-                                 dict(nx=2048, ny=2048, nz=1024)])
+                                 dict(nx=2048, ny=2048, nz=1024), dict(nx=4096, ny=4096, nz=1)])
 def test_bad_volumes_rejected(smc, vol):
     st, _ = _init_status(smc, _vol(smc, **vol), _vol(smc), _params(smc))
     assert st == smc.SMC_EINVAL
