@@ -598,9 +598,9 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
             const uint32_t nt1 = 1u + (tv << 9);
             const float fk = (float)k;
             if (TRI && LAYOUT != kLayoutRaw) {
-                // all PT samples: clamped coordinates (exact where inside, so every
-                // offset is valid), all loads issued before any use, then sums
-                // predicated on inside && FOV-valid && particle live for this tile
+                // all PT samples: coordinates and offsets, all loads issued before
+                // any use, then sums predicated on inside && FOV-valid && particle
+                // live for this tile
                 float fxa[PT], fya[PT], fza[PT];
                 uint32_t off[PT], ddy[PT], ddz[PT], vidx[PT];
                 bool in[PT];
@@ -632,6 +632,11 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                         off[p] = mad_u24(iz, a.zsb, mad_u24(iy, a.ysb, ix << kElemShift));
                         if (SOK) vidx[p] = off[p] >> kElemShift;
                     }
+                    // samples outside the source box would gather from wrapped
+                    // offsets near the volume (extra cache lines); send them
+                    // past the buffer's end, where the load reads zero unfetched
+                    if (LAYOUT == kLayoutOct || LAYOUT == kLayoutOctTile || LAYOUT == kLayoutLerp)
+                        off[p] = in[p] ? off[p] : 0xFFFFFFF0u;
                     if (LAYOUT == kLayoutPairX) ddy[p] = iy < (uint32_t)(a.sn1 - 1) ? a.ysb : 0u;
                     if (LAYOUT == kLayoutPairX || LAYOUT == kLayoutQuadXY)
                         ddz[p] = iz < (uint32_t)(a.sn2 - 1) ? a.zsb : 0u;
@@ -1014,7 +1019,8 @@ bool layout_fits(int layout, const int32_t sn[3]) {
     if (layout == kLayoutRaw) return true;
     // 32-bit buffer offsets; slice strides within the 24-bit multiplier
     const int32_t one[3] = {sn[0], sn[1], 1};
-    return packed_bytes(layout, sn) <= 0xFFFFFFFFull && packed_bytes(layout, one) < (1ull << 24);
+    // (offsets from 0xFFFFFFF0 up stay past the end: samples outside the box use them)
+    return packed_bytes(layout, sn) <= 0xFFFFFF00ull && packed_bytes(layout, one) < (1ull << 24);
 }
 
 size_t score_args_bytes() { return sizeof(KArgs); }
