@@ -296,8 +296,10 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
                                     (__float_as_uint(uz) < nzb);
                     msk[p] = in ? keep : 0u;
                     // 24-bit multiply-adds: exact inside (offsets below 2^32);
-                    // outside samples form arbitrary offsets, masked below
+                    // outside samples load from past the buffer's end (zero, no
+                    // cache lines touched) and are masked below
                     off[p] = mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, floor_u32(ux)));
+                    off[p] = in ? off[p] : 0xFFFFFFF0u;
                 }
                 uint32_t val[PT];
 #pragma unroll
