@@ -56,23 +56,43 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()
 
 
-def pmc_traffic():
-    """HBM-side bytes per warp-and-score launch from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, each scaled by its copy-kernel factor),
-    or None when the summary is missing or the kernel sources changed since."""
+def pmc_values():
+    """The values recorded in the committed counter summary, or {} when it is
+    missing or the kernel sources changed since it was taken."""
     if not os.path.exists(PMC_SUMMARY):
-        return None
+        return {}
     vals = {}
     with open(PMC_SUMMARY) as fh:
         for line in fh:
             if line.startswith("    ") and ":" in line:
                 k, v = line.strip().split(":", 1)
                 vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources_sha256") != kernel_sources_hash():
+        return {}
+    return vals
+
+
+def pmc_traffic():
+    """HBM-side bytes per warp-and-score launch from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by its copy-kernel factor),
+    or None when the summary is missing or the kernel sources changed since."""
+    vals = pmc_values()
     try:
-        if vals["kernel_sources_sha256"] != kernel_sources_hash():
-            return None
         return (float(vals["fetch_kib_per_dispatch"]) * float(vals["fetch_copy_factor"]) +
                 float(vals["write_kib_per_dispatch"]) * float(vals["write_copy_factor"])) * 1024.0
+    except (KeyError, ValueError):
+        return None
+
+
+def pmc_gather_path():
+    """On-chip gather-path figures per warp-and-score launch from the same
+    summary (L1 cache-line lookups, L1 -> L2 read requests, busy fractions), or
+    None."""
+    vals = pmc_values()
+    keys = ("l1_tag_lookups_per_dispatch", "l2_read_requests_per_dispatch", "l1_lookups_per_cu_clock",
+            "td_busy_frac", "ta_busy_frac", "valu_insts_per_cu_clock")
+    try:
+        return {k: float(vals[k]) for k in keys}
     except (KeyError, ValueError):
         return None
 
@@ -104,9 +124,29 @@ def cpu_baseline(pair, prm, target_s: float):
     t0 = time.perf_counter()
     pb.score(prm, x[:n2])
     dt = time.perf_counter() - t0
+    # one core, on a sample a quarter as long
+    oracle.set_threads(1)
+    try:
+        n1 = max(1, int(n2 / threads * 0.25))
+        t0 = time.perf_counter()
+        pb.score(prm, x[:n1])
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return dict(value=n2 * V / dt, unit="evals/s", cores=threads, kind="oracle",
                 sample=f"{n2} prior particles x {V} target voxels, one trilinear NCC evaluation each "
-                       f"({dt:.1f} s)")
+                       f"({dt:.1f} s)",
+                single_core_value=n1 * V / dt1, single_core_sample=f"{n1} particles ({dt1:.1f} s)",
+                host_cpu=model, host_logical_cpus=os.cpu_count())
 
 
 def main():
@@ -204,6 +244,7 @@ def main():
     achieved_tops = evals_per_launch * OPS_PER_EVAL / (score_launch_ms * 1e-3) / 1e12
     gather_gbs = evals_per_launch * GATHER_BYTES_PER_EVAL / (score_launch_ms * 1e-3) / 1e9
     traffic = pmc_traffic()
+    gpath = pmc_gather_path()
     line = {
         "metric": "particle×voxel evals/s",
         "value": value,
@@ -228,6 +269,9 @@ def main():
                      "ops_per_eval": OPS_PER_EVAL, "evals_per_launch": evals_per_launch,
                      "kernel_ms_per_launch": score_launch_ms, "launches": prof["score_launches"],
                      "gather_GBs": gather_gbs,
+                     "gather_path": None if gpath is None else dict(
+                         gpath, l1_lines_GBs=gpath["l1_tag_lookups_per_dispatch"] * 128.0 / (score_launch_ms * 1e-3) / 1e9,
+                         note="from the committed rocprofv3 counter summary; lines of 128 B"),
                      "filter_ms_per_launch": prof["filter_ms"] / max(1, prof["filter_launches"])},
         "final_score": est["score"],
     }

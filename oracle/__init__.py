@@ -104,6 +104,7 @@ def lib():
             "or_warp_apply": (None, [P(_Vol), d, C.c_int, u8, C.c_int32, C.c_int32, C.c_int32,
                                      C.c_double, C.c_double, C.c_double]),
             "or_num_threads": (C.c_int, []),
+            "or_set_threads": (None, [C.c_int]),
             "or_joint_histogram": (None, [P(_Vol), P(_Vol), f32, u64]),
             "or_mi_score": (C.c_double, [u64]),
             "or_mi_log": (C.c_double, [C.c_double]),
@@ -452,3 +453,8 @@ def warp_apply(src, M, trilinear, out_shape_xyz, out_spacing=(1.0, 1.0, 1.0)) ->
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (n < 1: all)."""
+    lib().or_set_threads(int(n))

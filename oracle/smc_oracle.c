@@ -1122,3 +1122,13 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the following parallel loops (n < 1: all processors). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
