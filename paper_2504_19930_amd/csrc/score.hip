@@ -261,8 +261,9 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
         // prepared source bytes through a bounds-checked buffer with 32-bit
         // offsets: an outside sample may form any offset, its result is masked
         const uint32_t sn0 = (uint32_t)a.sn0, sn01 = (uint32_t)a.sn0 * (uint32_t)a.sn1;
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<uint8_t *>(a.src), (short)0, a.sn0 * a.sn1 * a.sn2, kBufferWord3);
+        const int nbytes = a.sn0 * a.sn1 * a.sn2;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(a.src), (short)0, nbytes, kBufferWord3);
         // nearest (the words carry +0.5): inside iff 0 <= u < n, one unsigned
         // compare of bit patterns per axis (coordinates are never -0)
         const uint32_t nxb = __float_as_uint((float)a.sn0), nyb = __float_as_uint((float)a.sn1),
@@ -299,7 +300,7 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
                     // outside samples load from past the buffer's end (zero, no
                     // cache lines touched) and are masked below
                     off[p] = mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, floor_u32(ux)));
-                    off[p] = in ? off[p] : 0xFFFFFFF0u;
+                    off[p] = in ? off[p] : nbytes;
                 }
                 uint32_t val[PT];
 #pragma unroll
@@ -635,10 +636,10 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                         if (SOK) vidx[p] = off[p] >> kElemShift;
                     }
                     // samples outside the source box would gather from wrapped
-                    // offsets near the volume (extra cache lines); send them
-                    // past the buffer's end, where the load reads zero unfetched
+                    // offsets near the volume (extra cache lines); send them to
+                    // the buffer's end, where the load reads zero unfetched
                     if (LAYOUT == kLayoutOct || LAYOUT == kLayoutOctTile || LAYOUT == kLayoutLerp)
-                        off[p] = in[p] ? off[p] : 0xFFFFFFF0u;
+                        off[p] = in[p] ? off[p] : a.src_bytes;
                     if (LAYOUT == kLayoutPairX) ddy[p] = iy < (uint32_t)(a.sn1 - 1) ? a.ysb : 0u;
                     if (LAYOUT == kLayoutPairX || LAYOUT == kLayoutQuadXY)
                         ddz[p] = iz < (uint32_t)(a.sn2 - 1) ? a.zsb : 0u;
@@ -1021,7 +1022,7 @@ bool layout_fits(int layout, const int32_t sn[3]) {
     if (layout == kLayoutRaw) return true;
     // 32-bit buffer offsets; slice strides within the 24-bit multiplier
     const int32_t one[3] = {sn[0], sn[1], 1};
-    // (offsets from 0xFFFFFFF0 up stay past the end: samples outside the box use them)
+    // (below 4 GiB by a margin, so a load at the end offset cannot wrap)
     return packed_bytes(layout, sn) <= 0xFFFFFF00ull && packed_bytes(layout, one) < (1ull << 24);
 }
 
