@@ -301,3 +301,23 @@ def test_min_overlap_gives_minus_inf(orc):
                min_overlap_frac=0.5)
     z = pb.score(prm, np.array([[0, 0, 0, 0, 0, 0], [0, 0, 0, 15.0, 0, 0]]))
     assert np.isfinite(z[0]) and z[1] == -np.inf
+
+
+def test_scores_do_not_depend_on_thread_count(orc):
+    """The oracle's parallel loop over particles gives the same scores on one
+    thread as on all of them (the CPU baseline times both)."""
+    pair = synth.speckle_pair(side=32, seed=9, trans=3.0)
+    prm = dict(n_particles=24, n_iters=1, score="ncc", interp="trilinear", sigma_score=0.02,
+               limit=list(np.deg2rad([10.0] * 3)) + [3.0] * 3, sigma0=[0.01] * 6)
+    x = orc.init_particles(prm)
+    pb = orc.Problem(orc.Volume(pair["src"], fov=pair["src_fov"]), orc.Volume(pair["tgt"]))
+    threads = orc.num_threads()
+    want = pb.score(prm, x)
+    orc.set_threads(1)
+    try:
+        assert orc.num_threads() == 1
+        got = pb.score(prm, x)
+    finally:
+        orc.set_threads(threads)
+    assert orc.num_threads() == threads
+    assert np.array_equal(got, want)
