@@ -291,7 +291,10 @@ smc_status smc_set_proposal(smc_ctx *ctx, const double mean[6], const double log
  * it after the caller's stream and the caller's stream after it. */
 typedef struct smc_batch smc_batch;
 
-/* src, tgt and p are arrays of n_pairs (1 .. 4096).  Syncs once per pair. */
+/* src, tgt and p are arrays of n_pairs (1 .. 4096).  All trilinear image
+ * pairs take the first image pair's launch tuning and all mask pairs the
+ * first mask pair's particles per group (one kernel instance serves a
+ * class); SMC_EINVAL if a pair cannot take it.  Syncs once per pair. */
 smc_status smc_batch_init(smc_batch **out, uint32_t n_pairs, const smc_volume *src, const smc_volume *tgt,
                           const smc_params *p, void *hip_stream);
 /* New prior seeds for the next run (one per pair; NULL keeps them). */
