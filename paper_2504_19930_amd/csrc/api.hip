@@ -129,6 +129,11 @@ struct smc_ctx {
     bool has_sentinel[kLayouts] = {};
     FilterState f{};
     uint32_t k_done = 0;
+    // the current particles are a draw from the uniform prior box (spread over
+    // the whole limits): their first evaluation gathers from the octet layout
+    // when the lerp layout is configured (smaller elements suit the dispersed
+    // cloud, whose footprint streams from beyond the L2s)
+    bool prior_dispersed = false;
     // target |T| and FOV voxel count of this pair (the score constants pool them over frames)
     uint64_t tgt_on = 0, tgt_count = 0;
     // multi-frame score: further frame pairs, each prepared by a context of its
@@ -165,9 +170,16 @@ struct smc_ctx {
         return SMC_OK;
     }
 
-    // filter == true: only the sums the filter uses must be exact (masks: a, c)
+    // layout of a launch over a dispersed cloud (see prior_dispersed)
+    int dispersed_layout() const {
+        return mode == kModeImageTrilinear && layout == kLayoutLerp && packed[kLayoutOct] ? kLayoutOct : layout;
+    }
+
+    // filter == true: only the sums the filter uses must be exact (masks: a, c);
+    // dispersed == true: the particles are spread over the prior box
     ScoreLaunch score_launch(const float *words, unsigned long long *sums, uint32_t p0, uint32_t np,
-                             bool filter = false) const {
+                             bool filter = false, bool dispersed = false) const {
+        const int layout = dispersed ? dispersed_layout() : this->layout;
         ScoreLaunch L;
         L.mode = mode;
         L.zchunk = zchunk;
@@ -260,6 +272,11 @@ uint64_t splitmix64(uint64_t x) {
 // validity gather); if none is free, pack plainly and keep the gather.
 smc_status prepare_layout(smc_ctx *c, int layout) {
     if (c->mode != kModeImageTrilinear || layout == kLayoutRaw || c->packed[layout]) return SMC_OK;
+    if (layout == kLayoutLerp && layout_fits(kLayoutOct, c->sn)) {
+        // the octets serve the first evaluation of a dispersed prior
+        const smc_status so = prepare_layout(c, kLayoutOct);
+        if (so != SMC_OK) return so;
+    }
     smc_status st;
     if ((st = c->alloc((uint8_t **)&c->packed[layout], packed_bytes(layout, c->sn))) != SMC_OK) return st;
     uint64_t sent = 0;
@@ -304,6 +321,7 @@ smc_status launch_prior(smc_ctx *c) {
     HIP_TRY(launch_fill_u64(c->f.sums, 6ull * (c->f.n + 1), c->stream));
     HIP_TRY(launch_init_particles(c->f, c->stream));
     c->k_done = 0;
+    c->prior_dispersed = !c->f.has_proposal;
     return SMC_OK;
 }
 
@@ -328,13 +346,13 @@ smc_status ensure_eval(smc_ctx *c, uint32_t n) {
 // frame pair, then every further frame pair of a multi-frame score (integer
 // sums, so the pooled result does not depend on the order).
 hipError_t launch_score_frames(smc_ctx *c, const float *words, unsigned long long *sums, uint32_t *hist,
-                               uint32_t p0, uint32_t np, bool filter) {
+                               uint32_t p0, uint32_t np, bool filter, bool dispersed = false) {
     const bool mi = c->p.score == SMC_SCORE_MI;
-    ScoreLaunch L = c->score_launch(words, sums, p0, np, filter);
+    ScoreLaunch L = c->score_launch(words, sums, p0, np, filter, dispersed);
     if (mi) L.hist = hist;
     hipError_t e = launch_score(L, c->stream);
     for (size_t q = 0; q < c->frames.size() && e == hipSuccess; ++q) {
-        ScoreLaunch F = c->frames[q]->score_launch(words, sums, p0, np, filter);
+        ScoreLaunch F = c->frames[q]->score_launch(words, sums, p0, np, filter, dispersed);
         if (mi) F.hist = hist;
         e = launch_score(F, c->stream);
     }
@@ -527,8 +545,10 @@ smc_status smc_step(smc_ctx *c, uint32_t n_iters) {
     if ((st = set_device(c)) != SMC_OK) return c->mark(st);
     for (uint32_t it = 0; it < n_iters; ++it) {
         const uint32_t k = c->k_done + 1;
-        hipError_t e = timed(c, c->ev_score,
-                             [&] { return launch_score_frames(c, c->f.words, c->f.sums, c->hist, 0, c->f.n + 1, true); });
+        const bool dispersed = k == 1 && c->prior_dispersed;
+        hipError_t e = timed(c, c->ev_score, [&] {
+            return launch_score_frames(c, c->f.words, c->f.sums, c->hist, 0, c->f.n + 1, true, dispersed);
+        });
         if (e == hipSuccess) e = timed(c, c->ev_filter, [&] { return launch_filter(c->f, k, c->stream); });
         if (e == hipSuccess && k == c->f.n_iters) {
             e = launch_score_frames(c, c->f.words, c->f.sums, c->hist, c->f.n, 1, true);
@@ -712,6 +732,7 @@ smc_status smc_set_particles(smc_ctx *c, const double *states, uint32_t k_done) 
     // the host copy must outlive the upload
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->k_done = k_done;
+    c->prior_dispersed = false;  // a caller's particles: the configured layout throughout
     return SMC_OK;
 }
 
@@ -775,6 +796,7 @@ smc_status smc_set_state(smc_ctx *c, const void *buf, size_t len) {
     HIP_TRY(launch_fill_u64(c->f.sums, 6ull * (n + 1), c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->k_done = (uint32_t)h.k_done;
+    c->prior_dispersed = false;
     return SMC_OK;
 }
 
@@ -935,7 +957,9 @@ smc_status smc_autotune(smc_ctx *c, uint32_t reps, double *best_ms) {
                 if ((result = smc_set_tuning(c, lay, pt, depths[q])) != SMC_OK) break;
                 double cost = 0.0;
                 for (int set = 0; set < 2 && result == SMC_OK; ++set) {
-                    ScoreLaunch L = c->score_launch(set == 0 ? c->f.words : c->w_eval, c->s_eval, 0, np, true);
+                    // (the prior set is scored as smc_step's first iteration would score it)
+                    ScoreLaunch L = c->score_launch(set == 0 ? c->f.words : c->w_eval, c->s_eval, 0, np, true,
+                                                    set == 0 && c->prior_dispersed);
                     if (c->p.score == SMC_SCORE_MI) L.hist = c->hist_eval;
                     double tot = 0.0;
                     for (uint32_t r = 0; r <= reps && result == SMC_OK; ++r) {
