@@ -203,7 +203,8 @@ smc_status smc_set_frames(smc_ctx *ctx, uint32_t n_extra, const smc_volume *src_
  * tiles cull more exactly -- a tile whose image cannot reach the source, or
  * in the filter the source mask's bounding box, is skipped -- at the cost of
  * more partial sums).  A negative value keeps the current setting.  Defaults
- * come from measurements on MI355X.  A packed layout addresses its source
+ * come from measurements on MI355X: 4 particles per group; tile depth 16 for
+ * masks and 256 for images.  A packed layout addresses its source
  * with 32-bit offsets: SMC_EINVAL if the packed source reaches 4 GiB or one
  * packed slice 16 MiB.  smc_init starts from layout 5, else 3 if 5 does
  * not fit, else 0. */

@@ -29,7 +29,9 @@ thread_local std::string g_err;
 // (measured on MI355X: packed octets, 4 particles per workgroup; see smc_autotune)
 constexpr int kDefaultLayout = kLayoutLerp;
 constexpr int kDefaultPT = 4;
-constexpr int kDefaultZChunk = 32;
+// default tile depths, from measurements on MI355X: masks 16 (culling against
+// the source mask's bounding box pays at shallow tiles), images 256
+constexpr int kDefaultZChunkMask = 16, kDefaultZChunkImage = 256;
 
 smc_status fail(smc_status st, const char *fmt, ...) {
     char buf[512];
@@ -122,7 +124,7 @@ struct smc_ctx {
     int32_t sn[3] = {0, 0, 0}, tn[3] = {0, 0, 0};
     const uint8_t *src = nullptr, *src_fov = nullptr, *tgt = nullptr, *tgt_fov = nullptr;
     uint8_t *src_prep = nullptr, *tgt_prep = nullptr, *src_ok = nullptr;
-    int layout = kDefaultLayout, pt = kDefaultPT, zchunk = kDefaultZChunk;
+    int layout = kDefaultLayout, pt = kDefaultPT, zchunk = kDefaultZChunkMask;
     int32_t box_lo[3] = {1, 1, 1}, box_hi[3] = {-1, -1, -1};  // source mask bounding box (empty)
     void *packed[kLayouts] = {};
     uint64_t sentinel[kLayouts] = {};  // per packed layout: value marking elements outside the source FOV
@@ -417,6 +419,7 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
     c->tgt_fov = tgt->fov;
     c->mode = p->score == SMC_SCORE_DICE ? kModeMask
               : (p->interp == SMC_INTERP_TRILINEAR ? kModeImageTrilinear : kModeImageNearest);
+    c->zchunk = c->mode == kModeMask ? kDefaultZChunkMask : kDefaultZChunkImage;
     const int64_t vs = (int64_t)src->nx * src->ny * src->nz;
     const int64_t vt = (int64_t)tgt->nx * tgt->ny * tgt->nz;
     const uint32_t n = p->n_particles, K = p->n_iters;
