@@ -166,6 +166,38 @@ def test_full_filter_image_ncc_and_ssd(smc, orc):
         _compare_runs(smc, orc, pair, prm, src_fov=pair["src_fov"])
 
 
+def test_whole_registration_same_under_every_layout(smc, orc):
+    """A full image registration gives bit-identical particles, log-weights,
+    ancestors and estimate whatever the source layout (with the lerp layout
+    the first iteration over the uniform prior gathers from the octets), and
+    the same as a run whose prior came from smc_set_particles (scored with
+    the configured layout throughout)."""
+    pair = synth.speckle_pair(side=36, seed=21, trans=3.0)
+    prm = config.default_params("ncc", 160, 4, 20.0, 3.0, seed=6)
+    ref = None
+    for layout in ("lerp", "oct", "octtile", "quadxy", "raw"):
+        r = _reg(smc, pair, prm, src_fov=pair["src_fov"])
+        r.tune(layout, 4, 256)
+        r.reset(6)
+        r.run()
+        got = (r.particles(), r.estimate()["params"])
+        if ref is None:
+            ref = got
+            x0 = orc.init_particles(prm)
+        else:
+            for k in ("states", "logw", "ancestors"):
+                assert np.array_equal(got[0][k], ref[0][k]), (layout, k)
+            assert np.array_equal(got[1], ref[1]), layout
+        r.close()
+    r = _reg(smc, pair, prm, src_fov=pair["src_fov"])
+    r.tune("lerp", 4, 256)
+    r.set_particles(x0, 0)
+    r.run()
+    assert np.array_equal(r.particles()["states"], ref[0]["states"])
+    assert np.array_equal(r.estimate()["params"], ref[1])
+    r.close()
+
+
 def test_wide_rotation_filter_matches_oracle(smc, orc):
     """Wide-rotation mode: an off-centre ellipsoid turned by 178 degrees
     about z, rz searched over the whole circle (wrapped prediction), and an
