@@ -113,6 +113,31 @@ def test_warp_trilinear_vs_scipy_interior(orc, img):
         assert np.all(out[~ok] == 0)
 
 
+def test_warp_trilinear_vs_torch_grid_sample_interior(orc, img):
+    """The same check against PyTorch's grid_sample (trilinear, corners
+    aligned: normalised coordinate -1 at voxel 0 and +1 at voxel n - 1), a
+    second library implementation of the interpolation."""
+    import torch
+    rng = np.random.default_rng(18)
+    shp = img.shape[::-1]
+    vol = torch.from_numpy(img.astype(np.float64))[None, None]
+    for _ in range(3):
+        p = np.concatenate([rng.uniform(-0.3, 0.3, 3), rng.uniform(-2, 2, 3)])
+        M = orc.phys_matrix(p, shp)
+        out = orc.warp_apply(img, M, True, shp).astype(int)
+        u = _affine_u(M, shp)
+        grid = np.stack([2.0 * u[d] / (shp[d] - 1) - 1.0 for d in range(3)], -1)  # (z, y, x, 3) as (x, y, z)
+        val = torch.nn.functional.grid_sample(vol, torch.from_numpy(grid)[None], mode="bilinear",
+                                              padding_mode="border", align_corners=True)[0, 0].numpy()
+        ok = np.ones(img.shape, bool)
+        for d, n in enumerate(shp):
+            ok &= (u[d] >= 0) & (u[d] <= n - 1)
+        near_tie = np.abs(val - np.floor(val) - 0.5) < 1e-3
+        exact = ok & ~near_tie
+        assert exact.sum() > 200
+        assert np.array_equal(out[exact], np.floor(val[exact] + 0.5).astype(int))
+
+
 def test_trilinear_reproduces_affine_ramp(orc):
     # trilinear interpolation is exact on affine intensity fields
     n = 16
