@@ -139,9 +139,17 @@ def test_proposal_prior_and_filter_match_oracle(smc, orc):
     assert np.array_equal(g["ancestors"], o["ancestors"])
     assert np.allclose(g["states"], o["states"], rtol=0, atol=1e-12)
     assert np.allclose(r.estimate()["params"], o["est"], atol=1e-12)
+    # without the proposal the context is the plain filter again: same prior,
+    # no importance correction, the plain oracle's run
     r.set_proposal(None)
     r.reset(21)
     assert np.array_equal(r.particles()["states"], orc.init_particles(prm))
+    r.run()
+    o = orc.smc_run(pair["src"], pair["tgt"], prm)
+    g = r.particles()
+    assert np.array_equal(g["ancestors"], o["ancestors"])
+    assert np.allclose(g["states"], o["states"], rtol=0, atol=1e-12)
+    assert np.allclose(r.estimate()["params"], o["est"], atol=1e-12)
 
 
 def test_trained_proposal_reaches_plain_dice_with_less_work(smc):
