@@ -149,6 +149,107 @@ def cpu_baseline(pair, prm, target_s: float):
                 host_cpu=model, host_logical_cpus=os.cpu_count())
 
 
+def _batch_pair(spec):
+    import synth
+    p = synth.make_batch_pair(spec)
+    return dict(src=p["src"], tgt=p["tgt"], src_fov=p.get("src_fov"))
+
+
+def other_workload(name, steps, warmup):
+    """The full-size mask registration (lv224) and the 64-pair batch
+    (batch64), timed the same way; they document the other configurations and
+    are not the headline line (that is the default workload)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2504_19930_amd import binding, config
+    binding.lib()
+    torch.cuda.set_device(0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    if name == "lv224":
+        log("generating the 224x208x176 LV sequence (20 frames, masks and speckle) ...")
+        seq = synth.lv_sequence(seed=3, n_frames=20, speckle=True)
+        prm = config.workload_params("lv224")
+        N, K, V = prm["n_particles"], prm["n_iters"], seq["tgt"].size
+        reg = binding.Registration(dev(seq["src"]), dev(seq["tgt"]), prm)
+        sm, ss = dev(seq["src_masks"]), dev(seq["src_speckle"])
+        out_m = torch.empty((20,) + seq["tgt"].shape, dtype=torch.uint8, device="cuda")
+        out_s = torch.empty_like(out_m)
+
+        def step(s):
+            reg.reset(1000 + s)
+            reg.step(K)
+            est = reg.estimate()
+            binding.warp_apply(binding.volume(sm[0]), est["matrix"], "nearest", out_m, n_frames=20,
+                               src_frame_stride=V, dst_frame_stride=V)
+            binding.warp_apply(binding.volume(ss[0]), est["matrix"], "trilinear", out_s, n_frames=20,
+                               src_frame_stride=V, dst_frame_stride=V)
+            return est
+
+        for w in range(warmup):
+            step(w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            est = step(warmup + s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        evals = float(N) * V * K * steps
+        line = {"metric": "particle×voxel evals/s", "value": evals / wall, "unit": "evals/s", "n_gpus": 1,
+                "steps": steps, "warmup": warmup, "ms_per_step": wall * 1e3 / steps, "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "u8 masks, fp32 coordinates", "data": "synthetic",
+                "config": {"workload": "lv224: 224x208x176 ED LV masks, N=4096, K=40, Dice, nearest; one step = "
+                                       "one registration + warp_apply of 20 mask and 20 speckle frames",
+                           "tuning": reg.tuning()},
+                "final_score": est["score"]}
+        reg.close()
+    else:
+        import multiprocessing as mp
+        specs = synth.batch_pairs(64, seed=4)
+        log("generating the 64 batch pairs ...")
+        with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+            vols = list(pool.imap(_batch_pair, specs))
+        pairs, evals = [], 0.0
+        for spec, v in zip(specs, vols):
+            if spec["kind"] == "mask":
+                prm = config.default_params("dice", spec["n_particles"], 30, 15.0, 8.0 * spec["side"] / 64,
+                                            seed=spec["pair"])
+            else:
+                prm = config.default_params("ncc", spec["n_particles"], 30, 20.0, 12.0 * spec["side"] / 160,
+                                            seed=spec["pair"])
+            q = dict(src=dev(v["src"]), tgt=dev(v["tgt"]), params=prm)
+            if v["src_fov"] is not None:
+                q["src_fov"] = dev(v["src_fov"])
+            pairs.append(q)
+            evals += spec["n_particles"] * v["tgt"].size * 30
+        b = binding.Batch(pairs)
+        log("autotuning ...")
+        b.autotune(3)
+        kinds = {spec["kind"]: i for i, spec in reversed(list(enumerate(specs)))}
+        tunings = {k: binding.smc_get_tuning(b.pair(i)) for k, i in kinds.items()}
+        log(f"tunings: {tunings}")
+        for w in range(warmup):
+            b.set_seeds(np.arange(64) + 100 + w)
+            b.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            b.set_seeds(np.arange(64) + 200 + s)
+            b.run()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        line = {"metric": "particle×voxel evals/s", "value": evals * steps / wall, "unit": "evals/s", "n_gpus": 1,
+                "steps": steps, "warmup": warmup, "ms_per_step": wall * 1e3 / steps, "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "u8, fp32 coordinates", "data": "synthetic",
+                "config": {"workload": "batch64: 64 pairs, cubic sides 96..224, N in {1024..8192}, K=30, half "
+                                       "shell masks (Dice) and half speckle images (NCC); one step = one graph "
+                                       "launch of every registration", "evals_per_step": evals,
+                           "tuning": tunings}}
+        b.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +263,8 @@ def main():
     ap.add_argument("--tuning", default=DEFAULT_TUNING,
                     help="layout,particles_per_group,tile_depth of the warp-and-score launch")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch instead of --tuning")
+    ap.add_argument("--workload", default="speckle160", choices=["speckle160", "lv224", "batch64"],
+                    help="speckle160 (the headline line); lv224 or batch64 time the other configurations")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 256 MiB (three times), to scale HBM byte counters")
     args = ap.parse_args()
@@ -179,6 +282,14 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the registration path "
               f"runs on a single MI355X, see DESIGN.md for how it would shard)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload != "speckle160":
+        import torch
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            sys.exit(1)
+        other_workload(args.workload, args.steps, args.warmup)
+        return
 
     import numpy as np
     import torch

@@ -213,7 +213,7 @@ smc_status smc_get_tuning(smc_ctx *ctx, int32_t *layout, int32_t *particles_per_
 
 /* Autotuner: time every candidate tuning (layouts for trilinear images;
  * particles per group 4 / 8; tile depths) on this context's own volumes with
- * HIP events (reps launches each, on a scratch sum buffer) over two particle
+ * HIP events (the fastest of reps launches each, on a scratch sum buffer) over two particle
  * sets -- the current particles (after smc_init, the prior) and a cloud
  * concentrated within 5 % of the limits around x0, standing in for the
  * iterations after the first -- and apply the tuning with the least time per

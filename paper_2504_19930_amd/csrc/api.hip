@@ -964,7 +964,7 @@ smc_status smc_autotune(smc_ctx *c, uint32_t reps, double *best_ms) {
                     ScoreLaunch L = c->score_launch(set == 0 ? c->f.words : c->w_eval, c->s_eval, 0, np, true,
                                                     set == 0 && c->prior_dispersed);
                     if (c->p.score == SMC_SCORE_MI) L.hist = c->hist_eval;
-                    double tot = 0.0;
+                    double best_t = 1e30;  // the fastest of reps launches: robust to interference
                     for (uint32_t r = 0; r <= reps && result == SMC_OK; ++r) {
                         float ms = 0.0f;
                         if (launch_fill_u64(c->s_eval, 6ull * np, c->stream) != hipSuccess ||
@@ -972,9 +972,9 @@ smc_status smc_autotune(smc_ctx *c, uint32_t reps, double *best_ms) {
                             hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
                             result = fail(SMC_EDEVICE, "autotune launch failed");
-                        if (r > 0) tot += ms;  // the first launch warms caches
+                        if (r > 0) best_t = std::min(best_t, (double)ms);  // the first launch warms caches
                     }
-                    cost += (set == 0 ? 1.0 : w_conc) * tot / reps;
+                    cost += (set == 0 ? 1.0 : w_conc) * best_t;
                 }
                 const double avg = cost / (1.0 + w_conc);  // per launch over a registration
                 if (avg < best.ms) best = TuneVal{lay, pt, depths[q], avg};
