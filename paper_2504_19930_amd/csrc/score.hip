@@ -241,7 +241,9 @@ __device__ __forceinline__ uint32_t round_half_up_u32(float x) {
 // Target byte: bit 0 = inside the target FOV, bit 1 = mask on (and in FOV).
 // Per particle two packed counters: acc1 = n | a << 16, acc2 = b_ov | c << 16
 // (each half counts at most one voxel per z step, and a z-chunk < 2^16).
-template <int PT>
+// AC: only a and c (what Dice uses; the filter's launches), as twice the
+// counts: acc1 = 2 a, acc2 = 2 c; n and b_ov are left at zero.
+template <int PT, bool AC = false>
 __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t by) {
     const Tile t = tile_of<PT>(a, bx, by);
     const uint32_t live = live_mask<PT>(a, t, bx);
@@ -283,11 +285,11 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
                 const uint32_t tb = tslab8[(uint32_t)(k - kb) * kThreads + col];
                 const uint32_t keep = (tb & 1u) ? 3u : 0u;
                 const bool ton = (tb & 2u) != 0u;
+                // AC: the on bit (2) where the target voxel is in its FOV / on
+                const uint32_t ka = tb & 1u ? 2u : 0u, kc = tb & 2u;
                 const float fk = (float)k;
                 // offsets of all PT samples first, then every load, then the sums
-                // the inside flags travel as vector masks (keep & ~0 or 0): eight
-                // or more particles' lane masks would not fit the scalar registers
-                uint32_t off[PT], msk[PT];
+                uint32_t off[PT];
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
                     const float ux = fmaf(ax[p], fk, mx[p]);
@@ -295,10 +297,10 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
                     const float uz = fmaf(az[p], fk, mz[p]);
                     const bool in = ((live >> p) & 1u) & (__float_as_uint(ux) < nxb) & (__float_as_uint(uy) < nyb) &
                                     (__float_as_uint(uz) < nzb);
-                    msk[p] = in ? keep : 0u;
                     // 24-bit multiply-adds: exact inside (offsets below 2^32);
-                    // outside samples load from past the buffer's end (zero, no
-                    // cache lines touched) and are masked below
+                    // outside samples (and particles culled for this tile) load
+                    // from the buffer's end: zero, no cache lines touched, so they
+                    // count nothing
                     off[p] = mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, floor_u32(ux)));
                     off[p] = in ? off[p] : nbytes;
                 }
@@ -307,13 +309,17 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
                 for (int p = 0; p < PT; ++p) val[p] = __builtin_amdgcn_raw_buffer_load_b8(rs, off[p], 0, 0);
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
-                    // v in 0..3 (bit 0 in both FOVs, bit 1 also on); inc = (v & 1) +
-                    // (v >> 1) 2^16 = v + (v >> 1) (2^16 - 2).  Selects rather than a
-                    // branch on the flag, which would pull the load into the branch
-                    const uint32_t v = val[p] & msk[p];
-                    const uint32_t inc = mad_u24v(v >> 1, 65534u, v);
-                    acc1[p] += inc;
-                    acc2[p] += ton ? inc : 0u;
+                    if constexpr (AC) {
+                        acc1[p] += val[p] & ka;
+                        acc2[p] += val[p] & kc;
+                    } else {
+                        // v in 0..3 (bit 0 in both FOVs, bit 1 also on); inc = (v & 1) +
+                        // (v >> 1) 2^16 = v + (v >> 1) (2^16 - 2)
+                        const uint32_t v = val[p] & keep;
+                        const uint32_t inc = mad_u24v(v >> 1, 65534u, v);
+                        acc1[p] += inc;
+                        acc2[p] += ton ? inc : 0u;
+                    }
                 }
             }
         }
@@ -322,10 +328,10 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
-        const uint32_t n = wave_sum(acc1[p] & 0xFFFFu);
-        const uint32_t aa = wave_sum(acc1[p] >> 16);
-        const uint32_t b = wave_sum(acc2[p] & 0xFFFFu);
-        const uint32_t c = wave_sum(acc2[p] >> 16);
+        const uint32_t n = AC ? 0u : wave_sum(acc1[p] & 0xFFFFu);
+        const uint32_t aa = AC ? wave_sum(acc1[p]) >> 1 : wave_sum(acc1[p] >> 16);
+        const uint32_t b = AC ? 0u : wave_sum(acc2[p] & 0xFFFFu);
+        const uint32_t c = AC ? wave_sum(acc2[p]) >> 1 : wave_sum(acc2[p] >> 16);
         if (lane == 0) {
             red[wave][p][0] = n;
             red[wave][p][1] = aa;
@@ -837,11 +843,11 @@ __device__ __forceinline__ void xcd_order(uint32_t b, uint32_t total, uint32_t g
     *by = w - *bx * groups;
 }
 
-template <int PT>
+template <int PT, bool AC>
 __global__ __launch_bounds__(kThreads) void k_score_mask(const KArgs a) {
     uint32_t bx, by;
     xcd_order(blockIdx.x, gridDim.x, (a.np + PT - 1) / PT, &bx, &by);
-    mask_body<PT>(a, bx, by);
+    mask_body<PT, AC>(a, bx, by);
 }
 
 // The octet variants with four particles per workgroup fit 72 VGPRs without
@@ -919,7 +925,7 @@ void k_batch_score(const BatchArgs b) {
                 const uint32_t local = g - b.offs[d];
                 const uint32_t ng = (a.np + PT - 1) / PT;
                 const uint32_t bx = local / ng, by = local - bx * ng;
-                if (MODE == kModeMask) mask_body<PT>(a, bx, by);
+                if (MODE == kModeMask) mask_body<PT, true>(a, bx, by);  // the filter's launches
                 else image_body<PT, LAYOUT, true, VMODE>(a, bx, by);
             }
             __syncthreads();  // next_item is read by all before thread 0 takes the next
@@ -1006,7 +1012,7 @@ ScoreKernel pick_tri_layout(int layout, int vmode) {
 
 template <int PT>
 ScoreKernel pick(const ScoreLaunch &L) {
-    if (L.mode == kModeMask) return k_score_mask<PT>;
+    if (L.mode == kModeMask) return L.cull_box ? k_score_mask<PT, true> : k_score_mask<PT, false>;
     const bool sok = L.src_ok != nullptr;
     if (L.mode == kModeImageNearest)
         return sok ? k_score_image<PT, kLayoutRaw, false, 1> : k_score_image<PT, kLayoutRaw, false, 0>;
