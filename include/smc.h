@@ -193,9 +193,9 @@ smc_status smc_set_frames(smc_ctx *ctx, uint32_t n_extra, const smc_volume *src_
  * (one 128-byte cache line per tile, so a rotated footprint touches fewer
  * lines), 5 the octet cell stored ready for the x-interpolations (four
  * starts and four steps times 256 in half precision, 16 bytes, one gather
- * and fewer instructions per sample; layout 3 is prepared beside it and
+ * and fewer instructions per sample; layout 4 is prepared beside it and
  * serves the first iteration over a prior drawn from the uniform box, whose
- * dispersed particles gather faster from the smaller elements); packed
+ * dispersed particles gather faster from the smaller, tiled elements); packed
  * layouts cost 2, 4, 8 or 16 bytes per source voxel of device memory,
  * prepared on the stream.  particles_per_group: particles sharing one pass
  * over a target column, 4, 8 or 16.  tile_depth: target

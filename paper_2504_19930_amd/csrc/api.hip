@@ -132,9 +132,10 @@ struct smc_ctx {
     FilterState f{};
     uint32_t k_done = 0;
     // the current particles are a draw from the uniform prior box (spread over
-    // the whole limits): their first evaluation gathers from the octet layout
-    // when the lerp layout is configured (smaller elements suit the dispersed
-    // cloud, whose footprint streams from beyond the L2s)
+    // the whole limits): their first evaluation gathers from the tiled octets
+    // when the lerp layout is configured (smaller elements, fewer lines per
+    // gather: they suit the dispersed cloud, whose footprint streams from
+    // beyond the L2s)
     bool prior_dispersed = false;
     // target |T| and FOV voxel count of this pair (the score constants pool them over frames)
     uint64_t tgt_on = 0, tgt_count = 0;
@@ -174,7 +175,8 @@ struct smc_ctx {
 
     // layout of a launch over a dispersed cloud (see prior_dispersed)
     int dispersed_layout() const {
-        return mode == kModeImageTrilinear && layout == kLayoutLerp && packed[kLayoutOct] ? kLayoutOct : layout;
+        return mode == kModeImageTrilinear && layout == kLayoutLerp && packed[kLayoutOctTile] ? kLayoutOctTile
+                                                                                               : layout;
     }
 
     // filter == true: only the sums the filter uses must be exact (masks: a, c);
@@ -274,9 +276,9 @@ uint64_t splitmix64(uint64_t x) {
 // validity gather); if none is free, pack plainly and keep the gather.
 smc_status prepare_layout(smc_ctx *c, int layout) {
     if (c->mode != kModeImageTrilinear || layout == kLayoutRaw || c->packed[layout]) return SMC_OK;
-    if (layout == kLayoutLerp && layout_fits(kLayoutOct, c->sn)) {
-        // the octets serve the first evaluation of a dispersed prior
-        const smc_status so = prepare_layout(c, kLayoutOct);
+    if (layout == kLayoutLerp && layout_fits(kLayoutOctTile, c->sn)) {
+        // the tiled octets serve the first evaluation of a dispersed prior
+        const smc_status so = prepare_layout(c, kLayoutOctTile);
         if (so != SMC_OK) return so;
     }
     smc_status st;

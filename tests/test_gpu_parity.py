@@ -169,7 +169,7 @@ def test_full_filter_image_ncc_and_ssd(smc, orc):
 def test_whole_registration_same_under_every_layout(smc, orc):
     """A full image registration gives bit-identical particles, log-weights,
     ancestors and estimate whatever the source layout (with the lerp layout
-    the first iteration over the uniform prior gathers from the octets), and
+    the first iteration over the uniform prior gathers from the tiled octets), and
     the same as a run whose prior came from smc_set_particles (scored with
     the configured layout throughout)."""
     pair = synth.speckle_pair(side=36, seed=21, trans=3.0)
