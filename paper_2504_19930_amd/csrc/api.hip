@@ -1094,6 +1094,12 @@ struct smc_batch {
     uint32_t kmax_all = 0, max_threads = 0;
     struct Class {
         BatchPlan plan{};
+        // the first iteration over uniform priors (image classes whose pairs
+        // all score a dispersed prior from one other layout): same items,
+        // arguments for that layout
+        BatchPlan plan_first{};
+        bool has_first = false;
+        void *fargs = nullptr;
         std::vector<uint32_t> members;
         void *args = nullptr;
         uint32_t *offs = nullptr, *kmax = nullptr, *lists = nullptr;
@@ -1136,6 +1142,7 @@ int device_cus() {
 // volume) and the lists stay balanced whatever the mix of pairs.
 smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode, int vmode) {
     const uint32_t n = (uint32_t)C.members.size();
+    C.has_first = false;
     if (n == 0) {
         C.plan = BatchPlan{};  // an empty class launches nothing (also after a re-plan)
         return SMC_OK;
@@ -1200,6 +1207,31 @@ smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode, int vmode) {
     // persistent grid: as many workgroups as stay resident, a multiple of the 8 XCDs
     const uint32_t per_cu = (uint32_t)batch_blocks_per_cu(C.plan);
     C.plan.grid = 8 * (((uint32_t)device_cus() * per_cu + 7) / 8);
+    if (mode == kModeImageTrilinear) {
+        // a first-iteration plan when every pair scores its uniform prior from
+        // the same other layout with the same items and FOV mode
+        std::vector<uint8_t> fargs(ab * n);
+        bool ok = true;
+        int flayout = -1;
+        for (uint32_t q = 0; q < n && ok; ++q) {
+            const smc_ctx *c = b->pairs[C.members[q]];
+            const ScoreLaunch F = c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true, true);
+            if (q == 0) flayout = F.layout;
+            ok = !c->f.has_proposal && F.layout == flayout && F.layout != layout && F.pt == pt &&
+                 score_vmode(F) == vmode && score_items(F) == offs[q + 1] - offs[q];
+            if (ok) score_args(F, fargs.data() + ab * q);
+        }
+        if (ok) {
+            if ((st = b->alloc((uint8_t **)&C.fargs, fargs.size())) != SMC_OK) return st;
+            HIP_TRY(hipMemcpy(C.fargs, fargs.data(), fargs.size(), hipMemcpyHostToDevice));
+            C.plan_first = C.plan;
+            C.plan_first.layout = flayout;
+            C.plan_first.pairs = C.fargs;
+            const uint32_t fper = (uint32_t)batch_blocks_per_cu(C.plan_first);
+            C.plan_first.grid = 8 * (((uint32_t)device_cus() * fper + 7) / 8);
+            C.has_first = true;
+        }
+    }
     return SMC_OK;
 }
 
@@ -1244,7 +1276,10 @@ smc_status record_run(smc_batch *b) {
             HIP_TRY(launch_fill_u64((unsigned long long *)b->cls[q].plan.counters, 4ull * std::max(1u, b->kmax_all),
                                     b->stream));
     for (uint32_t k = 1; k <= b->kmax_all; ++k) {
-        for (int q = 0; q < 4; ++q) HIP_TRY(launch_batch_score(b->cls[q].plan, k, b->stream));
+        for (int q = 0; q < 4; ++q) {
+            const smc_batch::Class &C = b->cls[q];
+            HIP_TRY(launch_batch_score(k == 1 && C.has_first ? C.plan_first : C.plan, k, b->stream));
+        }
         for (uint32_t i : b->singles) {
             smc_ctx *c = b->pairs[i];
             if (k <= c->f.n_iters) HIP_TRY(launch_score_frames(c, c->f.words, c->f.sums, c->hist, 0, c->f.n + 1, true));
