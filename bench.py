@@ -280,7 +280,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the registration path "
-              f"runs on a single MI355X, see DESIGN.md for how it would shard)", file=sys.stderr)
+              f"runs on a single MI355X; sharding by pair or by particle is a design note, not built)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload != "speckle160":
