@@ -305,6 +305,19 @@ def test_speckle160_full_size_sampled(smc, orc):
     assert abs(z - est["score"]) <= 1e-12
 
 
+def test_speckle160_two_full_iterations_match_oracle(smc, orc):
+    """The throughput workload at full size in the benchmark's launch
+    configuration (lerp elements, four particles per group, full-depth tiles;
+    the prior scored from the tiled octets): two whole iterations -- every
+    particle scored, weighted, resampled, predicted and scored again -- give
+    the oracle's ancestors, log-weights, states and estimates (about 2e10
+    oracle evaluations)."""
+    pair = synth.speckle_pair(side=160, seed=2)
+    prm = config.workload_params("speckle160", n_iters=2)
+    r, _ = _compare_runs(smc, orc, pair, prm, src_fov=pair["src_fov"])
+    assert r.tuning() == dict(layout=smc.LAYOUTS["lerp"], particles_per_group=4, tile_depth=256)
+
+
 def test_lv224_full_size_sampled_and_warp_all_frames(smc, orc):
     import torch
     seq = synth.lv_sequence(seed=3, frames=[0, 5, 10], n_frames=20)
