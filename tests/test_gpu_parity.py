@@ -318,6 +318,16 @@ def test_speckle160_two_full_iterations_match_oracle(smc, orc):
     assert r.tuning() == dict(layout=smc.LAYOUTS["lerp"], particles_per_group=4, tile_depth=256)
 
 
+def test_lv224_two_full_iterations_match_oracle(smc, orc):
+    """The full-size mask volumes (224 x 208 x 176, Dice, default tuning)
+    with N = 1024 particles: two whole iterations match the oracle's
+    ancestors, log-weights, states and estimates (about 1.7e10 oracle
+    evaluations)."""
+    seq = synth.lv_sequence(seed=3, frames=[0], speckle=False)
+    prm = config.workload_params("lv224", n_iters=2, n_particles=1024)
+    _compare_runs(smc, orc, dict(src=seq["src"], tgt=seq["tgt"]), prm)
+
+
 def test_lv224_full_size_sampled_and_warp_all_frames(smc, orc):
     import torch
     seq = synth.lv_sequence(seed=3, frames=[0, 5, 10], n_frames=20)
