@@ -427,6 +427,38 @@ def test_batch_pairs_equal_single_runs_across_replays(smc, orc):
     b.close()
 
 
+def test_autotuned_batch_of_larger_pairs_equals_single_runs(smc):
+    """A batch of larger uneven pairs (sides 64..144, N 512..2048), autotuned
+    per class, so that the per-XCD item queues run long lists and workgroups
+    take items from other XCDs' lists: every pair equals its single-context
+    run (default tuning) bit for bit."""
+    specs = [("image", 144, 2048), ("mask", 128, 1024), ("image", 96, 512), ("mask", 64, 2048),
+             ("image", 112, 1024), ("mask", 144, 512), ("image", 64, 2048), ("mask", 96, 1024)]
+    pairs, host = [], []
+    for i, (kind, side, n) in enumerate(specs):
+        if kind == "mask":
+            pr = synth.shell_pair(seed=60 + i, side=side)
+            prm = config.default_params("dice", n, 3, 15.0, 8.0 * side / 64, seed=300 + i, pair_id=i)
+            pairs.append(dict(src=dev(pr["src"]), tgt=dev(pr["tgt"]), params=prm))
+        else:
+            pr = synth.speckle_pair(side=side, seed=60 + i, trans=12.0 * side / 160)
+            prm = config.default_params("ncc", n, 3, 20.0, 12.0 * side / 160, seed=300 + i, pair_id=i)
+            pairs.append(dict(src=dev(pr["src"]), tgt=dev(pr["tgt"]), src_fov=dev(pr["src_fov"]), params=prm))
+        host.append((pr, prm))
+    b = smc.Batch(pairs)
+    b.autotune(1)
+    b.run()
+    for i, (pr, prm) in enumerate(host):
+        r = _reg(smc, pr, prm, src_fov=pr.get("src_fov"))
+        r.run()
+        gb, gs = b.particles(i), r.particles()
+        assert np.array_equal(gb["states"], gs["states"]), i
+        assert np.array_equal(gb["ancestors"], gs["ancestors"]), i
+        assert np.array_equal(b.estimate(i)["params"], r.estimate()["params"]), i
+        r.close()
+    b.close()
+
+
 def test_batch_with_mi_and_wide_pairs(smc, orc):
     """A batch mixing a moment-based image pair, an MI pair (run as its own
     launches inside the graph) and a wide-rotation mask pair: each equals its
