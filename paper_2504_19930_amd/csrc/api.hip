@@ -964,7 +964,7 @@ smc_status smc_autotune(smc_ctx *c, uint32_t reps, double *best_ms) {
                 for (int set = 0; set < 2 && result == SMC_OK; ++set) {
                     // (the prior set is scored as smc_step's first iteration would score it)
                     ScoreLaunch L = c->score_launch(set == 0 ? c->f.words : c->w_eval, c->s_eval, 0, np, true,
-                                                    set == 0 && c->prior_dispersed);
+                                                    set == 0 && c->prior_dispersed && c->k_done == 0);
                     if (c->p.score == SMC_SCORE_MI) L.hist = c->hist_eval;
                     double best_t = 1e30;  // the fastest of reps launches: robust to interference
                     for (uint32_t r = 0; r <= reps && result == SMC_OK; ++r) {
