@@ -579,6 +579,13 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
         uint32_t nt[PT];
 #pragma unroll
         for (int p = 0; p < PT; ++p) nt[p] = 0u;
+        // mutual information: each thread holds its current run of samples
+        // falling into one bin (neighbouring slices often share a bin) and
+        // adds the run to the LDS histogram when the bin changes, so fewer
+        // lanes contend for the same LDS words
+        uint32_t rbin[HIST ? PT : 1], rcnt[HIST ? PT : 1];
+#pragma unroll
+        for (int p = 0; p < (HIST ? PT : 1); ++p) rbin[p] = rcnt[p] = 0u;
         // The target column block is staged in LDS a slab of kSlab slices at a
         // time with coalesced loads (four bytes per lane where rows are 4-byte
         // aligned): a gather costs the same whatever its width, and the
@@ -694,7 +701,15 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                         LAYOUT == kLayoutLerp ? round_half_up_u32(sv) : (uint32_t)fmaf(sv, 256.0f, 0.5f);
                     const bool valid = in[p] & (okv[p] != 0u);
                     if constexpr (HIST) {
-                        if (valid) atomicAdd(&lhist[p][(sfx0 >> 11) * kMiBins + (tv >> 3)], 1u);
+                        if (valid) {
+                            const uint32_t bin = (sfx0 >> 11) * kMiBins + (tv >> 3);
+                            if (bin != rbin[p]) {
+                                if (rcnt[p]) atomicAdd(&lhist[p][rbin[p]], rcnt[p]);
+                                rbin[p] = bin;
+                                rcnt[p] = 0u;
+                            }
+                            rcnt[p] += 1u;
+                        }
                     } else if (valid) {
                         // under the lane mask: no selects on the five updates
                         nt[p] += nt1;
@@ -782,6 +797,11 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
             }
         }
         }  // slabs
+        if constexpr (HIST) {
+#pragma unroll
+            for (int p = 0; p < PT; ++p)
+                if (rcnt[p]) atomicAdd(&lhist[p][rbin[p]], rcnt[p]);
+        }
 #pragma unroll
         for (int p = 0; p < PT; ++p) {
             acc[p].n += nt[p] & 511u;
