@@ -5,8 +5,8 @@
  * particle filter" (arXiv 2504.19930).
  *
  * The problem (Abstract; Methods, Registration, Eq. 1): given a source and a
- * target volume -- echo intensities or binary LV masks -- and an initial
- * approximation of the rotation and translation limits, estimate the rigid
+ * target volume -- echo intensities or binary LV masks -- and rough bounds on
+ * how far the rotation and the translation may range, estimate the rigid
  * transform (rx, ry, rz, tx, ty, tz) of Implementation Details (Euler 3D
  * transform, homogeneous matrix of Eq. 3) that best aligns the warped source
  * with the target, then apply it to every frame of the sequence.
@@ -84,7 +84,7 @@ typedef struct {
  * used here are documented readings (rotation / translation limits from the
  * Abstract, the rest tuned on synthetic data). */
 typedef struct {
-    uint32_t n_particles;    /* N, 1 .. 65536 */
+    uint32_t n_particles;    /* N, 1 .. 65535 (the resampling CDF, a sum of N values <= 2^48, is 64-bit) */
     uint32_t n_iters;        /* K >= 1: K evaluations, K-1 resample + predict steps */
     uint64_t seed;           /* Philox4x32-10 key */
     uint32_t pair_id;        /* third Philox counter word; distinguishes pairs of a batch */
@@ -154,13 +154,16 @@ smc_status smc_exhaustive(smc_ctx *ctx, const double lo[6], const double step[6]
                           double best_params[6], double *best_score, double *scores);
 
 /* Replace the particle set (host N x 6) as if k_done iterations had run;
- * for step-by-step replays and resumption.  Async. */
+ * for step-by-step replays and resumption.  The set is not treated as a
+ * proposal draw (its first update carries no importance correction).  Syncs. */
 smc_status smc_set_particles(smc_ctx *ctx, const double *states_n6, uint32_t k_done);
 
 /* Serialise / restore the whole filter state (particles, weights, estimate,
  * trace, iteration count).  smc_get_state with buf == NULL returns the size in
  * *len.  Restoring into a context made with the same inputs and parameters
- * continues bit-identically.  Both sync. */
+ * continues bit-identically.  The state holds no proposal densities: a set
+ * restored before its first update is treated as not drawn from a proposal.
+ * Both sync. */
 smc_status smc_get_state(smc_ctx *ctx, void *buf, size_t *len);
 smc_status smc_set_state(smc_ctx *ctx, const void *buf, size_t len);
 
@@ -280,9 +283,32 @@ smc_status smc_cnn_step(smc_cnn *net, float lr);
 void smc_cnn_destroy(smc_cnn *net);
 
 /* Draw the next prior (smc_reset) from the Gaussian N(mean, exp(logvar))
- * truncated to x0 +- limit instead of the uniform box, and correct the first
- * update by log p - log q.  mean == NULL returns to the uniform prior. */
+ * truncated to x0 +- limit instead of the uniform box; the first update of a
+ * set so drawn is corrected by log p - log q.  mean == NULL returns to the
+ * uniform prior for the next draw.  Neither changes the current particle set
+ * or its correction: a set drawn from the uniform box is never corrected, a
+ * set drawn from a proposal always is.  mean and logvar are host arrays of 6
+ * (radians, mm; logvar in [-60, 60]).  SMC_EINVAL on non-finite values. */
 smc_status smc_set_proposal(smc_ctx *ctx, const double mean[6], const double logvar[6]);
+
+/* Training label of the proposal network: the weighted particle cloud after
+ * the last completed iteration, summarised with the normalised weights
+ * exp(lw_i - max lw) of that iteration's evaluation (uniform when every
+ * log-weight is -inf) as its weighted mean and per-axis weighted variance,
+ * in units of the limits about x0: mean[d] = (xbar_d - x0_d) / L_d,
+ * var[d] = max(Var_d / L_d^2, var_floor).  Host outputs of 6.  Syncs.
+ * SMC_ESTATE before the first iteration; SMC_EINVAL on NULL outputs or a
+ * negative / non-finite var_floor. */
+smc_status smc_cloud_moments(smc_ctx *ctx, double var_floor, double mean[6], double var[6]);
+
+/* Set the proposal (as smc_set_proposal, for the next prior draw) from the
+ * network's 12 outputs (host FP32: 6 means and 6 log-variances in units of
+ * the limits): mean_d = x0_d + L_d clip(out_d, -1, 1), logvar_d =
+ * clip(out_{6+d}, -20, 2) + 2 log L_d + log var_scale, where var_scale > 0
+ * widens the predicted spread.  mean_out / logvar_out (host, may be NULL)
+ * receive the values set.  SMC_EINVAL on non-finite outputs or var_scale. */
+smc_status smc_set_proposal_from_network(smc_ctx *ctx, const float out[12], double var_scale, double mean_out[6],
+                                         double logvar_out[6]);
 
 /* ---- Batches: many registration pairs of uneven size and particle count
  * run together.  Every pair behaves exactly as its own smc_init /

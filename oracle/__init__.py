@@ -23,6 +23,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 SCORES = {"dice": 0, "ncc": 1, "ssd": 2, "mi": 3}
+# the resampling CDF sums floor(w 2^48) per particle in 64 bits (smc_oracle.c)
+MAX_PARTICLES = 65535
 
 
 def build(force: bool = True) -> str:
@@ -86,10 +88,12 @@ def lib():
             "or_loglik": (C.c_double, [C.c_double, C.c_int, C.c_double]),
             "or_normalise": (C.c_int, [C.c_uint32, d, d, d, d, P(C.c_double)]),
             "or_normalise_wide": (C.c_int, [C.c_uint32, d, d, d, d, d, P(C.c_double)]),
+            "or_cloud_moments": (None, [C.c_uint32, d, d, d, d, C.c_double, d, d]),
+            "or_proposal_from_network": (None, [f32, d, d, C.c_double, d, d]),
             "or_euler_quat": (None, [d, d]),
             "or_quat_R": (None, [d, d]),
             "or_R_euler": (None, [d, d]),
-            "or_resample": (None, [C.c_uint32, d, C.c_uint32, i32]),
+            "or_resample": (C.c_int, [C.c_uint32, d, C.c_uint32, i32]),
             "or_gauss6": (None, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, d]),
             "or_perturb": (None, [P(_Params), C.c_uint32, d, i32, d]),
             "or_init_particles": (None, [P(_Params), d]),
@@ -304,6 +308,26 @@ def normalise_wide(lw, x, x0):
     return dict(w=w, est=est, ess=ess.value, degenerate=bool(deg))
 
 
+def cloud_moments(lw, x, x0, limit, var_floor=0.0):
+    """Weighted mean and per-axis variance of a particle cloud in units of
+    the limits about x0 (the learned proposal's training label)."""
+    lw = np.ascontiguousarray(lw, float)
+    x = np.ascontiguousarray(x, float).reshape(-1, 6)
+    mean, var = np.zeros(6), np.zeros(6)
+    lib().or_cloud_moments(len(lw), lw, x, np.ascontiguousarray(x0, float), np.ascontiguousarray(limit, float),
+                           float(var_floor), mean, var)
+    return mean, var
+
+
+def proposal_from_network(out, x0, limit, var_scale):
+    """(mean, logvar) of the proposal the network's 12 outputs stand for."""
+    mean, logvar = np.zeros(6), np.zeros(6)
+    lib().or_proposal_from_network(np.ascontiguousarray(out, np.float32).reshape(12),
+                                   np.ascontiguousarray(x0, float), np.ascontiguousarray(limit, float),
+                                   float(var_scale), mean, logvar)
+    return mean, logvar
+
+
 def euler_quat(p) -> np.ndarray:
     q = np.zeros(4)
     lib().or_euler_quat(np.ascontiguousarray(np.resize(np.asarray(p, float), 6)), q)
@@ -325,7 +349,8 @@ def R_euler(R) -> np.ndarray:
 def resample(w, u32) -> np.ndarray:
     w = np.ascontiguousarray(w, float)
     anc = np.zeros(len(w), np.int32)
-    lib().or_resample(len(w), w, int(u32), anc)
+    if lib().or_resample(len(w), w, int(u32), anc) != 0:
+        raise ValueError(f"{len(w)} particles: resampling takes 1 .. {MAX_PARTICLES}")
     return anc
 
 
@@ -394,6 +419,8 @@ def filter_update(params: dict, k: int, x, z) -> dict:
     xn = np.zeros_like(x)
     ess = C.c_double()
     deg = lib().or_filter_update(C.byref(pr), int(k), x, z, None, lw, w, est, C.byref(ess), anc, xn)
+    if deg < 0:
+        raise ValueError(f"{n} particles: the filter takes 1 .. {MAX_PARTICLES}")
     return dict(lw=lw, w=w, est=est, ess=ess.value, anc=anc, x_next=xn, degenerate=bool(deg))
 
 
@@ -410,6 +437,8 @@ def smc_run(src, tgt, params: dict, fp64_mode=False, frames=None) -> dict:
     svs = (_Vol * len(pairs))(*[a.c() for a, _ in pairs])
     tvs = (_Vol * len(pairs))(*[b.c() for _, b in pairs])
     deg = lib().or_smc_run_frames(svs, tvs, len(pairs), C.byref(pr), est, ts, te, tx, x, lw, anc)
+    if deg < 0:
+        raise ValueError(f"{n} particles: the filter takes 1 .. {MAX_PARTICLES}")
     return dict(est=est, trace_score=ts, trace_ess=te, trace_est=tx, states=x, logw=lw, ancestors=anc,
                 degenerate=bool(deg))
 

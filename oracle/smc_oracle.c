@@ -47,6 +47,11 @@
 
 #define OR_MI_BINS 32 /* joint-histogram bins per axis of the MI score */
 
+/* Largest particle count.  Resampling sums q_i = floor(w_i 2^48) with
+ * w_i <= 1 (the largest weight is exactly 1) in a uint64: the total stays
+ * below 2^64 only for n < 2^16. */
+#define OR_MAX_PARTICLES 65535u
+
 /* ------------------------------------------------------------------ Philox */
 
 /* Philox4x32-10: ten rounds of (two 32x32->64 multiplies, xor with the other
@@ -808,6 +813,58 @@ int or_normalise(uint32_t n, const double *lw, const double *x, double *w, doubl
     return degenerate;
 }
 
+/* Label of the learned proposal (the target's addition, no paper passage):
+ * the weighted particle cloud summarised by its weighted mean and per-axis
+ * weighted variance, with the normalised weights of or_normalise, written in
+ * units of the limits about x0 -- mean (xbar - x0) / L, variance Var / L^2,
+ * floored at var_floor. */
+void or_cloud_moments(uint32_t n, const double *lw, const double *x, const double x0[6], const double limit[6],
+                      double var_floor, double mean[6], double var[6])
+{
+    double mx = -INFINITY;
+    for (uint32_t i = 0; i < n; ++i)
+        if (lw[i] > mx) mx = lw[i];
+    int flat = mx == -INFINITY;
+    double s = 0.0, xbar[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t i = 0; i < n; ++i) {
+        double w = flat ? 1.0 : exp(lw[i] - mx);
+        s += w;
+        for (int d = 0; d < 6; ++d) xbar[d] += w * x[6 * (size_t)i + d];
+    }
+    for (int d = 0; d < 6; ++d) xbar[d] = xbar[d] / s;
+    double dev[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t i = 0; i < n; ++i) {
+        double w = flat ? 1.0 : exp(lw[i] - mx);
+        for (int d = 0; d < 6; ++d) {
+            double e = x[6 * (size_t)i + d] - xbar[d];
+            dev[d] += w * e * e;
+        }
+    }
+    for (int d = 0; d < 6; ++d) {
+        mean[d] = (xbar[d] - x0[d]) / limit[d];
+        double v = dev[d] / s / (limit[d] * limit[d]);
+        var[d] = v > var_floor ? v : var_floor;
+    }
+}
+
+/* The proposal the network's outputs stand for (the target's addition): the
+ * outputs are a Gaussian in units of the limits about x0; the mean is clipped
+ * to the box, the log-variance to [-20, 2], and the variance widened by
+ * var_scale before it is turned back into radians / mm. */
+void or_proposal_from_network(const float out[12], const double x0[6], const double limit[6], double var_scale,
+                              double mean[6], double logvar[6])
+{
+    for (int d = 0; d < 6; ++d) {
+        double u = (double)out[d], l = (double)out[6 + d];
+        if (u < -1.0) u = -1.0;
+        if (u > 1.0) u = 1.0;
+        if (l < -20.0) l = -20.0;
+        if (l > 2.0) l = 2.0;
+        mean[d] = x0[d] + u * limit[d];
+        logvar[d] = l + 2.0 * log(limit[d]) + log(var_scale);
+    }
+}
+
 /* Normalisation as or_normalise, with the rotation of the estimate taken
  * from unit quaternions (wide-rotation mode): the particle quaternions are
  * put on the hemisphere of the first particle of largest log-weight, summed
@@ -847,8 +904,9 @@ int or_normalise_wide(uint32_t n, const double *lw, const double *x, const doubl
  * Q = sum q_i, C_i the inclusive prefix sums; with one uniform word U the
  * j-th pointer is (j + U / 2^32) Q / N and the ancestor of j is the first i
  * whose C_i exceeds it, i.e. C_i N 2^32 > (j 2^32 + U) Q (128-bit exact). */
-void or_resample(uint32_t n, const double *w, uint32_t u32, int32_t *anc)
+int or_resample(uint32_t n, const double *w, uint32_t u32, int32_t *anc)
 {
+    if (n < 1 || n > OR_MAX_PARTICLES) return -1;
     uint64_t *cdf = (uint64_t *)malloc(sizeof(uint64_t) * n);
     uint64_t run = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -865,6 +923,7 @@ void or_resample(uint32_t n, const double *w, uint32_t u32, int32_t *anc)
         anc[j] = (int32_t)i;
     }
     free(cdf);
+    return 0;
 }
 
 /* Reflect once at the limits box, then clamp. */
@@ -1004,6 +1063,7 @@ int or_filter_update(const or_params *pr, uint32_t k, const double *x, const dou
                      double *lw, double *w, double est[6], double *ess, int32_t *anc, double *x_next)
 {
     uint32_t n = pr->n_particles;
+    if (n < 1 || n > OR_MAX_PARTICLES) return -1;
     for (uint32_t i = 0; i < n; ++i) {
         lw[i] = or_loglik(z[i], pr->score, pr->sigma_score);
         /* importance correction of the proposal draw: log p - log q, p uniform */
@@ -1027,9 +1087,10 @@ int or_smc_run_frames(const or_vol *srcs, const or_vol *tgts, uint32_t nf, const
                       double est_out[6], double *trace_score, double *trace_ess, double *trace_est, double *x_out,
                       double *lw_out, int32_t *anc_out)
 {
+    uint32_t n = pr->n_particles;
+    if (n < 1 || n > OR_MAX_PARTICLES) return -1;
     or_problem *pbs = (or_problem *)malloc(sizeof(or_problem) * nf);
     for (uint32_t f = 0; f < nf; ++f) or_problem_init(&pbs[f], &srcs[f], &tgts[f]);
-    uint32_t n = pr->n_particles;
     double *x = (double *)malloc(sizeof(double) * 6 * n);
     double *xn = (double *)malloc(sizeof(double) * 6 * n);
     double *z = (double *)malloc(sizeof(double) * n);

@@ -31,7 +31,7 @@ EXPORTS = ("smc_init", "smc_reset", "smc_step", "smc_estimate", "smc_get_particl
            "smc_batch_pair", "smc_batch_destroy", "smc_cnn_create", "smc_cnn_set_params", "smc_cnn_get_params",
            "smc_cnn_input", "smc_cnn_read_input", "smc_cnn_forward", "smc_cnn_backward", "smc_cnn_step", "smc_cnn_destroy",
            "smc_set_proposal", "smc_exhaustive", "smc_autotune", "smc_batch_autotune", "smc_set_frames",
-           "smc_score_particles")
+           "smc_score_particles", "smc_cloud_moments", "smc_set_proposal_from_network")
 
 
 class SmcError(RuntimeError):
@@ -96,6 +96,8 @@ def lib():
             "smc_cnn_backward": [vp, u32, vp, vp, vp],
             "smc_cnn_step": [vp, C.c_float],
             "smc_set_proposal": [vp, vp, vp],
+            "smc_cloud_moments": [vp, dp, vp, vp],
+            "smc_set_proposal_from_network": [vp, vp, dp, vp, vp],
             "smc_exhaustive": [vp, vp, vp, vp, vp, vp, vp],
             "smc_autotune": [vp, u32, vp],
             "smc_batch_autotune": [vp, u32],
@@ -281,6 +283,21 @@ def smc_set_proposal(ctx, mean=None, logvar=None):
     _check(lib().smc_set_proposal(ctx, _ptr(m), _ptr(lv)))
 
 
+def smc_cloud_moments(ctx, var_floor=0.0):
+    """Weighted mean and variance of the particle cloud in units of the limits."""
+    mean, var = np.zeros(6), np.zeros(6)
+    _check(lib().smc_cloud_moments(ctx, float(var_floor), _ptr(mean), _ptr(var)))
+    return mean, var
+
+
+def smc_set_proposal_from_network(ctx, out, var_scale):
+    """Proposal from the network's 12 outputs; returns the (mean, logvar) set."""
+    o = np.ascontiguousarray(out, dtype=np.float32).reshape(12)
+    mean, logvar = np.zeros(6), np.zeros(6)
+    _check(lib().smc_set_proposal_from_network(ctx, _ptr(o), float(var_scale), _ptr(mean), _ptr(logvar)))
+    return mean, logvar
+
+
 def smc_set_tuning(ctx, layout=None, particles_per_group=None, tile_depth=None):
     lay = -1 if layout is None else (LAYOUTS[layout] if isinstance(layout, str) else int(layout))
     pt = -1 if particles_per_group is None else int(particles_per_group)
@@ -376,6 +393,12 @@ class Registration:
 
     def set_proposal(self, mean=None, logvar=None):
         smc_set_proposal(self.ctx, mean, logvar)
+
+    def set_proposal_from_network(self, out, var_scale):
+        return smc_set_proposal_from_network(self.ctx, out, var_scale)
+
+    def cloud_moments(self, var_floor=0.0):
+        return smc_cloud_moments(self.ctx, var_floor)
 
     def autotune(self, reps=3):
         ms = C.c_double()

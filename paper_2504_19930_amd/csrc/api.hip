@@ -71,7 +71,8 @@ smc_status check_volume(const smc_volume *v, const char *name) {
 
 smc_status check_params(const smc_params *p) {
     if (!p) return fail(SMC_EINVAL, "params is NULL");
-    if (p->n_particles < 1 || p->n_particles > 65536) return fail(SMC_EINVAL, "n_particles must be in 1..65536");
+    // the resampling CDF sums floor(w 2^48) <= 2^48 per particle in 64 bits
+    if (p->n_particles < 1 || p->n_particles > 65535) return fail(SMC_EINVAL, "n_particles must be in 1..65535");
     if (p->n_iters < 1 || p->n_iters > 100000) return fail(SMC_EINVAL, "n_iters must be in 1..100000");
     if (p->score < SMC_SCORE_DICE || p->score > SMC_SCORE_MI) return fail(SMC_EINVAL, "unknown score %d", p->score);
     if (p->interp != SMC_INTERP_NEAREST && p->interp != SMC_INTERP_TRILINEAR)
@@ -233,6 +234,8 @@ struct smc_ctx {
 };
 
 namespace {
+
+const int32_t kZeroFlag = 0;
 
 smc_status set_device(smc_ctx *c) {
     HIP_TRY(hipSetDevice(c->device));
@@ -732,6 +735,8 @@ smc_status smc_set_particles(smc_ctx *c, const double *states, uint32_t k_done) 
     if ((st = c->check_sticky()) != SMC_OK) return st;
     if ((st = set_device(c)) != SMC_OK) return c->mark(st);
     HIP_TRY(hipMemcpyAsync(c->f.x, states, 48ull * c->f.n, hipMemcpyHostToDevice, c->stream));
+    // a caller's set is not a proposal draw: no importance correction
+    HIP_TRY(hipMemcpyAsync(c->f.flags + 2, &kZeroFlag, sizeof kZeroFlag, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(launch_words(c->f.x, c->f.n, c->f.geom, c->f.nearest, c->f.words, c->stream));
     HIP_TRY(launch_fill_u64(c->f.sums, 6ull * (c->f.n + 1), c->stream));
     // the host copy must outlive the upload
@@ -796,6 +801,8 @@ smc_status smc_set_state(smc_ctx *c, const void *buf, size_t len) {
         HIP_TRY(hipMemcpyAsync(pc.dev, q, pc.bytes, hipMemcpyHostToDevice, c->stream));
         q += pc.bytes;
     }
+    // the state holds no proposal densities: a restored set gets no importance correction
+    HIP_TRY(hipMemcpyAsync(c->f.flags + 2, &kZeroFlag, sizeof kZeroFlag, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(launch_words(c->f.x, c->f.n, c->f.geom, c->f.nearest, c->f.words, c->stream));
     HIP_TRY(launch_words(c->f.est, 1, c->f.geom, c->f.nearest, c->f.words + 12 * n, c->stream));
     HIP_TRY(launch_fill_u64(c->f.sums, 6ull * (n + 1), c->stream));
@@ -1595,6 +1602,50 @@ void smc_cnn_destroy(smc_cnn *n) {
     (void)hipStreamSynchronize(n->stream);
     for (void *p : n->allocs) (void)hipFree(p);
     delete n;
+}
+
+smc_status smc_cloud_moments(smc_ctx *c, double var_floor, double mean[6], double var[6]) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (!mean || !var) return fail(SMC_EINVAL, "mean and var must not be NULL");
+    if (!(var_floor >= 0.0) || !isfinite(var_floor)) return fail(SMC_EINVAL, "var_floor must be finite and >= 0");
+    if (c->k_done == 0) return fail(SMC_ESTATE, "no iteration has run: the particles carry no weights yet");
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    if ((st = ensure_eval(c, 2)) != SMC_OK) return c->mark(st);
+    double m[12];
+    HIP_TRY(launch_cloud_moments(c->f, c->x_eval, c->stream));
+    HIP_TRY(hipMemcpyAsync(m, c->x_eval, sizeof m, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    // in units of the limits about x0, as the network predicts them
+    for (int d = 0; d < 6; ++d) {
+        const double L = c->f.limit[d];
+        mean[d] = (m[d] - c->f.x0[d]) / L;
+        var[d] = fmax(m[6 + d] / (L * L), var_floor);
+    }
+    return SMC_OK;
+}
+
+smc_status smc_set_proposal_from_network(smc_ctx *c, const float out[12], double var_scale, double mean_out[6],
+                                         double logvar_out[6]) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (!out) return fail(SMC_EINVAL, "out is NULL");
+    if (!(var_scale > 0.0) || !isfinite(var_scale)) return fail(SMC_EINVAL, "var_scale must be finite and positive");
+    for (int q = 0; q < 12; ++q)
+        if (!isfinite(out[q])) return fail(SMC_EINVAL, "network output %d is not finite", q);
+    double mean[6], logvar[6];
+    for (int d = 0; d < 6; ++d) {
+        const double L = c->f.limit[d];
+        const double u = fmin(fmax((double)out[d], -1.0), 1.0);
+        const double l = fmin(fmax((double)out[6 + d], -20.0), 2.0);
+        mean[d] = c->f.x0[d] + u * L;
+        logvar[d] = l + 2.0 * log(L) + log(var_scale);
+    }
+    const smc_status st = smc_set_proposal(c, mean, logvar);
+    if (st != SMC_OK) return st;
+    if (mean_out) memcpy(mean_out, mean, sizeof mean);
+    if (logvar_out) memcpy(logvar_out, logvar, sizeof logvar);
+    return SMC_OK;
 }
 
 smc_status smc_set_proposal(smc_ctx *c, const double mean[6], const double logvar[6]) {

@@ -268,12 +268,16 @@ __global__ __launch_bounds__(256) void k_bias_grad(const float *dY, int B, int C
 
 // Adam on FP32 master weights; refresh the bfloat16 copies of the
 // convolution weights ([0, n_bf16) of the flat parameter vector).
+// One Adam step (Kingma & Ba): m and v are the decayed first and second
+// moments of the gradient, c1 = 1 - b1^t and c2 = 1 - b2^t their bias
+// corrections.  The coefficients come from the host rounded once from FP64
+// (1 - b and 1 - b^t lose digits if formed from FP32 b).
 __global__ void k_adam(float *p, const float *g, float *m, float *v, uint16_t *pb, int64_t n, int64_t n_bf16,
-                       float lr, float b1, float b2, float c1, float c2, float eps) {
+                       float lr, float b1, float omb1, float b2, float omb2, float c1, float c2, float eps) {
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         const float gq = g[q];
-        const float mq = b1 * m[q] + (1.0f - b1) * gq;
-        const float vq = b2 * v[q] + (1.0f - b2) * gq * gq;
+        const float mq = b1 * m[q] + omb1 * gq;
+        const float vq = b2 * v[q] + omb2 * (gq * gq);
         m[q] = mq;
         v[q] = vq;
         const float w = p[q] - lr * (mq / c1) / (sqrtf(vq / c2) + eps);
@@ -374,10 +378,11 @@ hipError_t cnn_backward(const CnnBuffers &c, const uint16_t *input, int B, const
 }
 
 hipError_t cnn_adam(const CnnBuffers &c, float lr, int t, hipStream_t s) {
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - pow(b1, (double)t)), c2 = (float)(1.0 - pow(b2, (double)t));
     hipLaunchKernelGGL(k_adam, dim3(blocks(c.n_params)), dim3(256), 0, s, c.params, c.grads, c.adam_m, c.adam_v,
-                       c.wbf16, (int64_t)c.n_params, (int64_t)cnn_param_offset(8), lr, b1, b2, c1, c2, 1e-8f);
+                       c.wbf16, (int64_t)c.n_params, (int64_t)cnn_param_offset(8), lr, (float)b1, (float)(1.0 - b1),
+                       (float)b2, (float)(1.0 - b2), c1, c2, 1e-8f);
     return hipGetLastError();
 }
 

@@ -104,6 +104,7 @@ __device__ __forceinline__ void init_body(const FilterState &f, uint32_t i, uint
         particle_words(f.x0, f.geom, f.nearest, f.words + 12 * (size_t)f.n);
         f.flags[0] = 0;
         f.flags[1] = 0;
+        f.flags[2] = f.has_proposal ? 1 : 0;
     }
     const uint32_t nt = f.n_iters + 1;
     for (uint32_t q = i; q < nt; q += stride) {
@@ -138,13 +139,15 @@ __device__ __forceinline__ void filter_body(const FilterState &f, const uint32_t
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const uint32_t n = f.n;
 
-    // update: log-weights of the scores, and their maximum
+    // update: log-weights of the scores, and their maximum; a set drawn from
+    // the proposal carries the importance correction in its first update
+    const bool from_proposal = f.flags[2] != 0;
     double mx = -INFINITY;
     for (uint32_t i = tid; i < n; i += kFT) {
         int64_t m[6];
         for (int q = 0; q < 6; ++q) m[q] = (int64_t)f.sums[6 * (size_t)i + q];
         double l = log_likelihood(score_from_sums(m, f.sc), f.sc);
-        if (k == 1 && f.has_proposal) l = l + f.lq[i];
+        if (k == 1 && from_proposal) l = l + f.lq[i];
         f.lw[i] = l;
         mx = fmax(mx, l);
     }
@@ -319,6 +322,71 @@ __global__ __launch_bounds__(kFT) void k_filter_batch(const FilterState *fs, con
     if (k <= f.n_iters) filter_body(f, k);
 }
 
+// Weighted mean and per-axis weighted variance of the particle set under the
+// normalised weights exp(lw_i - max lw) of the last evaluation (uniform when
+// every log-weight is -inf): out[0..5] the mean, out[6..11] the variance,
+// in the filter's units.  One workgroup; FP64 tree sums.
+__global__ __launch_bounds__(kFT) void k_cloud_moments(const FilterState f, double *out) {
+    __shared__ double red[kFW][7];
+    __shared__ double bc[7];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const uint32_t n = f.n;
+    double mx = -INFINITY;
+    for (uint32_t i = tid; i < n; i += kFT) mx = fmax(mx, f.lw[i]);
+    mx = wave_max(mx);
+    if (lane == 0) red[wave][0] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        double v = red[0][0];
+        for (int w = 1; w < kFW; ++w) v = fmax(v, red[w][0]);
+        bc[0] = v;
+    }
+    __syncthreads();
+    const double M = bc[0];
+    const bool flat = M == -INFINITY;
+    // pass 1: total weight and weighted sums of the states
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t i = tid; i < n; i += kFT) {
+        const double w = flat ? 1.0 : exp(f.lw[i] - M);
+        acc[0] += w;
+        for (int d = 0; d < 6; ++d) acc[1 + d] += w * f.x[6 * (size_t)i + d];
+    }
+    for (int q = 0; q < 7; ++q) acc[q] = wave_add(acc[q]);
+    __syncthreads();
+    if (lane == 0)
+        for (int q = 0; q < 7; ++q) red[wave][q] = acc[q];
+    __syncthreads();
+    if (tid < 7) {
+        double v = 0.0;
+        for (int w = 0; w < kFW; ++w) v += red[w][tid];
+        bc[tid] = v;
+    }
+    __syncthreads();
+    const double total = bc[0];
+    double mean[6];
+    for (int d = 0; d < 6; ++d) mean[d] = bc[1 + d] / total;
+    // pass 2: weighted squared deviations from the mean
+    double dv[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t i = tid; i < n; i += kFT) {
+        const double w = flat ? 1.0 : exp(f.lw[i] - M);
+        for (int d = 0; d < 6; ++d) {
+            const double e = f.x[6 * (size_t)i + d] - mean[d];
+            dv[d] += w * (e * e);
+        }
+    }
+    for (int d = 0; d < 6; ++d) dv[d] = wave_add(dv[d]);
+    __syncthreads();
+    if (lane == 0)
+        for (int d = 0; d < 6; ++d) red[wave][d] = dv[d];
+    __syncthreads();
+    if (tid < 6) {
+        double v = 0.0;
+        for (int w = 0; w < kFW; ++w) v += red[w][tid];
+        out[tid] = mean[tid];
+        out[6 + tid] = v / total;
+    }
+}
+
 __global__ void k_ghost_final(const FilterState f) {
     int64_t m[6];
     for (int q = 0; q < 6; ++q) m[q] = (int64_t)f.sums[6 * (size_t)f.n + q];
@@ -439,6 +507,11 @@ hipError_t launch_init_batch(const FilterState *fs, uint32_t n_pairs, uint32_t m
 
 hipError_t launch_filter_batch(const FilterState *fs, uint32_t n_pairs, uint32_t k, hipStream_t s) {
     hipLaunchKernelGGL(k_filter_batch, dim3(n_pairs), dim3(kFT), 0, s, fs, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_cloud_moments(const FilterState &f, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_cloud_moments, dim3(1), dim3(kFT), 0, s, f, out);
     return hipGetLastError();
 }
 

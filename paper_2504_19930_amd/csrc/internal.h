@@ -128,9 +128,12 @@ struct FilterState {
     double *trace_score;      // K + 1
     double *trace_ess;        // K
     double *trace_est;        // 6 K
-    int32_t *flags;           // [0] degenerate weights seen, [1] at the latest iteration
-    // learned proposal: the prior draw comes from a Gaussian truncated to the
-    // limits box, and the first update adds log p - log q (p uniform)
+    // [0] degenerate weights seen, [1] at the latest iteration, [2] the current
+    // particle set is a draw from the proposal (its first update adds lq)
+    int32_t *flags;
+    // learned proposal: the next prior draw comes from a Gaussian truncated to
+    // the limits box; the draw records itself in flags[2], and the first update
+    // of such a set adds log p - log q (p uniform)
     int32_t has_proposal;
     double prop_mu[6], prop_sigma[6];
     double *lq;               // n: -log q(x_i) + const of the proposal draw
@@ -144,6 +147,9 @@ hipError_t launch_init_batch(const FilterState *states_dev, uint32_t n_pairs, ui
 hipError_t launch_filter_batch(const FilterState *states_dev, uint32_t n_pairs, uint32_t k, hipStream_t s);
 hipError_t launch_filter(const FilterState &f, uint32_t k, hipStream_t s);
 hipError_t launch_ghost_final(const FilterState &f, hipStream_t s);
+// Weighted mean (out[0..5]) and per-axis weighted variance (out[6..11]) of the
+// particle set under the normalised weights of the last evaluation.
+hipError_t launch_cloud_moments(const FilterState &f, double *out, hipStream_t s);
 hipError_t launch_words(const double *x, uint32_t n, const Geom &g, bool nearest, float *words, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, hipStream_t s);
 // Mutual information: scores of particles p0 .. p0 + np - 1 from their joint

@@ -52,10 +52,6 @@ def init_params(seed: int) -> np.ndarray:
     return out
 
 
-def limits():
-    return np.array([math.radians(ROT_DEG)] * 3 + [TRANS] * 3)
-
-
 # ------------------------------------------------------------------ data and labels
 
 def _gen(seed):
@@ -89,12 +85,11 @@ def make_training_set(n_pairs: int, seed0: int = 1_000_000, workers: int = 16, l
     return dict(src=src, tgt=tgt, src_mask=smask, tgt_mask=tmask, spacing=spacing)
 
 
-def label_with_smc(data, n_particles=256, n_iters=15, batch_pairs=256, seed=7, log=None):
+def label_with_smc(data, n_particles=256, n_iters=15, batch_pairs=256, seed=7, log=None, var_floor=1e-4):
     """Run the plain filter on every training pair (batched, one graph launch
-    per batch) and summarise its final weighted cloud: mean and variance in
-    units of the limits."""
+    per batch) and summarise its final weighted cloud (smc_cloud_moments):
+    mean and variance in units of the limits, the variance floored."""
     torch = _torch()
-    L = limits()
     n = len(data["src_mask"])
     mean = np.zeros((n, 6))
     var = np.zeros((n, 6))
@@ -109,15 +104,7 @@ def label_with_smc(data, n_particles=256, n_iters=15, batch_pairs=256, seed=7, l
         batch = binding.Batch(pairs)
         batch.run()
         for q, i in enumerate(idx):
-            part = batch.particles(q)
-            lw = part["logw"]
-            w = np.exp(lw - lw.max()) if np.isfinite(lw.max()) else np.ones_like(lw)
-            w /= w.sum()
-            x = part["states"]
-            m = (w[:, None] * x).sum(0)
-            v = (w[:, None] * (x - m) ** 2).sum(0)
-            mean[i] = m / L
-            var[i] = v / (L * L)
+            mean[i], var[i] = binding.smc_cloud_moments(batch.pair(q), var_floor)
         batch.close()
         if log:
             log(f"labels {min(n, b0 + batch_pairs)}/{n}")
@@ -126,12 +113,12 @@ def label_with_smc(data, n_particles=256, n_iters=15, batch_pairs=256, seed=7, l
 
 # ------------------------------------------------------------------ training
 
-def train(data, mean, var, epochs=8, batch=32, lr=1e-3, seed=0, holdout=512, log=None, var_floor=1e-4):
+def train(data, mean, var, epochs=8, batch=32, lr=1e-3, seed=0, holdout=512, log=None):
     torch = _torch()
     n = len(data["src"])
     src = torch.from_numpy(data["src"]).cuda()
     tgt = torch.from_numpy(data["tgt"]).cuda()
-    target = np.concatenate([mean, np.maximum(var, var_floor)], axis=1).astype(np.float32)
+    target = np.concatenate([mean, var], axis=1).astype(np.float32)
     net = binding.Cnn(max_batch=batch)
     net.set_params(init_params(seed))
     rng = np.random.default_rng(seed)
@@ -180,14 +167,12 @@ class Proposal:
         self.net.set_params(params)
         self.var_scale = var_scale
 
-    def predict(self, src_vol, tgt_vol, x0, limit, scale=1.0):
-        """Mean and log-variance of the transform for a (device) pair."""
+    def propose(self, reg, src_vol, tgt_vol, scale=1.0):
+        """Network forward on a (device) pair, then the registration's next
+        prior drawn from its prediction (smc_set_proposal_from_network).
+        Returns the (mean, logvar) that was set."""
         self.net.input(0, src_vol, tgt_vol, scale)
-        out = self.net.forward(1)[0].astype(np.float64)
-        L = np.asarray(limit, float)
-        mean = np.asarray(x0, float) + np.clip(out[:6], -1.0, 1.0) * L
-        logvar = np.clip(out[6:], -20.0, 2.0) + 2.0 * np.log(L) + math.log(self.var_scale)
-        return mean, logvar
+        return reg.set_proposal_from_network(self.net.forward(1)[0], self.var_scale)
 
     def close(self):
         self.net.close()
@@ -214,7 +199,6 @@ def time_to_dice(pair, params, n_plain=4096, n_learned=512, K=40, seed=0, tol=0.
     torch = _torch()
     src = torch.from_numpy(pair["src"]).cuda()
     tgt = torch.from_numpy(pair["tgt"]).cuda()
-    L = limits()
     out = {}
     # plain
     prm = default_params("dice", n_plain, K, ROT_DEG, TRANS, seed=seed)
@@ -236,8 +220,7 @@ def time_to_dice(pair, params, n_plain=4096, n_learned=512, K=40, seed=0, tol=0.
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     start.record()
-    mean, logvar = prop.predict(reg.src, reg.tgt, np.zeros(6), L, scale=1.0)
-    reg.set_proposal(mean, logvar)
+    mean, logvar = prop.propose(reg, reg.src, reg.tgt, scale=1.0)
     reg.reset(seed)
     ev = []
     _events_run(reg, K, ev)

@@ -121,6 +121,102 @@ def test_adam_training_reduces_loss(smc):
     net.close()
 
 
+def test_adam_steps_match_oracle(smc):
+    """Five backward + Adam steps on the GPU against the oracle's FP64 Adam fed
+    the same read-back gradients: the FP32 master weights agree to FP32
+    rounding, and the bfloat16 copies the forward pass uses are the rounded
+    master weights (a fresh network given the same weights computes the same
+    outputs bit for bit)."""
+    B, lr = 4, 2e-3
+    net = smc.Cnn(max_batch=B)
+    p32 = ocnn.init_params(11)
+    net.set_params(p32)
+    x, keep = _inputs(smc, net, B, seed=5)
+    rng = np.random.default_rng(9)
+    target = np.concatenate([rng.normal(0, 0.4, (B, 6)), rng.uniform(0.01, 0.2, (B, 6))], 1)
+    p, m, v = p32.astype(np.float64), np.zeros(p32.size), np.zeros(p32.size)
+    for t in range(1, 6):
+        _, g = net.backward(target, grads=True)
+        net.step(lr)
+        p, m, v = ocnn.adam(p, g.astype(np.float64), m, v, t, lr)
+        got = net.get_params().astype(np.float64)
+        err = np.abs(got - p)
+        # FP32 storage of the weights (2^-24 relative per step) and FP32 moment
+        # arithmetic (a few 1e-7 of the lr-sized update)
+        assert np.all(err <= 2.0 ** -24 * t * np.abs(p) + 1e-5 * lr), (t, float(err.max()))
+        moved = np.abs(got - p32) > 0
+        assert moved.mean() > 0.5, t
+    out = net.forward(B)
+    fresh = smc.Cnn(max_batch=B)
+    fresh.set_params(net.get_params())
+    x2, keep2 = _inputs(smc, fresh, B, seed=5)
+    assert np.array_equal(fresh.forward(B), out)
+    fresh.close()
+    net.close()
+
+
+def test_proposal_changes_only_the_next_prior(smc, orc):
+    """smc_set_proposal affects the next prior draw only: set on a context
+    whose particles came from the uniform box, the next steps are the plain
+    filter's (no importance correction); removed after a proposal draw, the
+    drawn set keeps its correction; a caller's particle set never gets one."""
+    pair = synth.shell_pair(seed=8, side=36)
+    prm = config.default_params("dice", 80, 3, 15.0, 5.0, seed=33)
+    mean = np.array([0.02, 0.01, -0.03, 0.6, -0.4, 0.2])
+    logvar = 2 * np.log(np.array([0.04, 0.04, 0.04, 0.9, 0.9, 0.9]))
+    plain = orc.smc_run(pair["src"], pair["tgt"], prm)
+    prop = orc.smc_run(pair["src"], pair["tgt"], dict(prm, proposal=dict(mean=list(mean), logvar=list(logvar))))
+    r = smc.Registration(dev(pair["src"]), dev(pair["tgt"]), prm)
+    r.set_proposal(mean, logvar)          # uniform prior already drawn
+    r.run()
+    g = r.particles()
+    assert np.array_equal(g["ancestors"], plain["ancestors"])
+    assert np.allclose(g["logw"], plain["logw"], rtol=1e-12, atol=1e-12)
+    r.reset(33)                           # draws from the proposal
+    r.set_proposal(None)                  # the drawn set keeps its correction
+    r.run()
+    g = r.particles()
+    assert np.array_equal(g["ancestors"], prop["ancestors"])
+    assert np.allclose(g["states"], prop["states"], rtol=0, atol=1e-12)
+    assert np.allclose(r.estimate()["params"], prop["est"], atol=1e-12)
+    # a caller's set (here the plain prior) is not corrected, proposal or not
+    r.set_proposal(mean, logvar)
+    r.set_particles(orc.init_particles(prm), 0)
+    r.run()
+    g = r.particles()
+    assert np.array_equal(g["ancestors"], plain["ancestors"])
+    assert np.allclose(r.estimate()["params"], plain["est"], atol=1e-12)
+    r.close()
+
+
+def test_cloud_label_and_network_proposal_match_oracle(smc, orc):
+    """The two library calls the learned path is built from: the training
+    label (smc_cloud_moments: the final weighted cloud in units of the
+    limits) equals the oracle's on the oracle's own run of the same pair, and
+    the proposal set from network outputs (smc_set_proposal_from_network)
+    equals the oracle's map, down to the prior it draws."""
+    pair = synth.shell_pair(seed=12, side=36)
+    x0 = [0.01, 0.0, -0.02, 0.5, 0.0, -0.5]
+    prm = config.default_params("dice", 150, 4, 15.0, 5.0, seed=3, x0=x0)
+    r = smc.Registration(dev(pair["src"]), dev(pair["tgt"]), prm)
+    with pytest.raises(smc.SmcError):
+        r.cloud_moments()  # no weights before the first iteration
+    r.run()
+    o = orc.smc_run(pair["src"], pair["tgt"], prm)
+    gm, gv = r.cloud_moments(1e-4)
+    om, ov = orc.cloud_moments(o["logw"], o["states"], x0, prm["limit"], 1e-4)
+    assert np.allclose(gm, om, rtol=1e-10, atol=1e-11)
+    assert np.allclose(gv, ov, rtol=1e-8, atol=1e-12)
+    out = np.array([0.3, -2.0, 0.1, -0.4, 0.9, 1.5, -3.0, -25.0, 0.5, -1.0, 3.0, -6.0], np.float32)
+    m, lv = r.set_proposal_from_network(out, 4.0)
+    om, olv = orc.proposal_from_network(out, x0, prm["limit"], 4.0)
+    assert np.allclose(m, om, rtol=0, atol=1e-15) and np.allclose(lv, olv, rtol=0, atol=1e-13)
+    r.reset(5)
+    x, _ = orc.init_proposal(dict(prm, seed=5, proposal=dict(mean=list(om), logvar=list(olv))))
+    assert np.allclose(r.particles()["states"], x, rtol=0, atol=1e-13)
+    r.close()
+
+
 def test_proposal_prior_and_filter_match_oracle(smc, orc):
     pair = synth.shell_pair(seed=6, side=40)
     prm = config.default_params("dice", 96, 4, 15.0, 5.0, seed=21)

@@ -387,6 +387,34 @@ def test_tuning_invariance(smc, orc):
         m.tune(None, 5)
 
 
+def test_fixed_point_rounding_tie_under_every_layout(smc, orc):
+    """The fixed-point sample is floor(256 s + 0.5) with the addition done in
+    FP32, as the oracle writes it.  The one FP32 value whose sum with 0.5
+    rounds up to the next integer is 256 s = 0.5 - 2^-25 (0.5 + that lies
+    halfway between 1 - 2^-24 and 1 and ties to 1), so an exact
+    floor(x + 0.5) would give 0 there and the FP32 recipe 1.  An identity
+    rotation with x translation 2^-9 - 2^-33 over a source whose value is its
+    x index puts exactly that value at every target voxel of the plane x = 0;
+    every layout must reproduce the oracle's sums."""
+    nx, ny, nz = 9, 6, 5
+    src = np.broadcast_to(np.arange(nx, dtype=np.uint8), (nz, ny, nx)).copy()
+    tgt = np.random.default_rng(3).integers(0, 256, (nz, ny, nx)).astype(np.uint8)
+    t = 2.0 ** -9 - 2.0 ** -33
+    x = np.array([[0.0, 0.0, 0.0, t, 0.0, 0.0], [0.0, 0.0, 0.0, 2.0 ** -9, 0.0, 0.0], np.zeros(6)])
+    w = orc.recipe_words(x[0], orc.Volume(src), orc.Volume(tgt), nn=False)
+    assert w[3] == np.float32(t)  # the x offset word carries the tie value exactly
+    want = _oracle_sums(orc, orc.Volume(src), orc.Volume(tgt), x, "trilinear")
+    # the oracle's FP32 addition rounds the tie up: s_fx = 1 on the x = 0 plane
+    assert want[0, 1] == want[1, 1]
+    prm = config.default_params("ncc", 4, 2, 10.0, 2.0)
+    r = _reg(smc, dict(src=src, tgt=tgt), prm)
+    for layout in ("raw", "pairx", "quadxy", "oct", "octtile", "lerp"):
+        for pt in (4, 8):
+            r.tune(layout, pt, 256)
+            assert np.array_equal(r.evaluate(x), want), (layout, pt)
+    r.close()
+
+
 def test_batch_pairs_equal_single_runs_across_replays(smc, orc):
     """Uneven pairs (mask and trilinear image, different sizes, particle and
     iteration counts) in one graph launch: every pair equals its own

@@ -55,7 +55,7 @@ def _init_status(smc, src, tgt, prm):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(n_particles=0), dict(n_particles=70000), dict(n_iters=0), dict(score="ncc", interp="nearest",
+    dict(n_particles=0), dict(n_particles=65536), dict(n_particles=70000), dict(n_iters=0), dict(score="ncc", interp="nearest",
                                                                           sigma_score=-1.0),
     dict(anneal=0.0), dict(anneal=1.5), dict(min_overlap_frac=2.0), dict(limit=[0.1, 0.1, 0.0, 1, 1, 1]),
     dict(sigma0=[-1.0] * 6), dict(x0=[float("nan")] + [0.0] * 5), dict(interp="trilinear"),

@@ -109,6 +109,30 @@ def test_param_count_and_layout():
     assert np.array_equal(cnn.flatten(parts).astype(np.float32), p)
 
 
+def test_adam_matches_torch_over_several_steps():
+    """Five steps of the oracle's Adam against torch.optim.Adam in FP64
+    (beta 0.9 / 0.999, eps 1e-8): parameters and both moment estimates.
+    The gradients change from step to step and span magnitudes down to the
+    scale of eps, so swapped betas, bias-corrected moments returned in place
+    of the raw ones, or eps inside the square root would all show."""
+    rng = np.random.default_rng(12)
+    n = 64
+    p0 = rng.normal(size=n)
+    grads = [rng.normal(size=n) * 10.0 ** rng.uniform(-9, 1, n) for _ in range(5)]
+    lr = 0.01
+    w = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([w], lr=lr, betas=(0.9, 0.999), eps=1e-8)
+    p, m, v = p0.copy(), np.zeros(n), np.zeros(n)
+    for t, g in enumerate(grads, start=1):
+        w.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        p, m, v = cnn.adam(p, g, m, v, t, lr)
+        st = opt.state[w]
+        assert np.allclose(p, w.detach().numpy(), rtol=1e-13, atol=1e-15), t
+        assert np.allclose(m, st["exp_avg"].numpy(), rtol=1e-13, atol=0), t
+        assert np.allclose(v, st["exp_avg_sq"].numpy(), rtol=1e-13, atol=0), t
+
+
 def test_adam_step_direction():
     p = np.array([1.0, -2.0])
     g = np.array([0.5, -0.25])

@@ -100,6 +100,22 @@ def test_equal_weights_resample_to_identity(orc):
         assert np.array_equal(orc.resample(np.ones(33), u), np.arange(33))
 
 
+def test_resampling_at_the_particle_limit(orc):
+    """Flat weights (every particle scored alike, e.g. no overlap anywhere) at
+    the largest particle count still give every particle one copy: the CDF
+    total, N 2^48, stays below 2^64.  One particle more would wrap it, so the
+    oracle (like the library) refuses N = 65536."""
+    n = orc.MAX_PARTICLES
+    assert n == 2 ** 16 - 1
+    for u in (0, 2 ** 32 - 1):
+        assert np.array_equal(orc.resample(np.ones(n), u), np.arange(n))
+    with pytest.raises(ValueError):
+        orc.resample(np.ones(n + 1), 0)
+    with pytest.raises(ValueError):
+        orc.filter_update(dict(n_particles=n + 1, n_iters=2, limit=[0.1] * 6, sigma_score=0.01, sigma0=[0.0] * 6),
+                          1, np.zeros((n + 1, 6)), np.zeros(n + 1))
+
+
 # ------------------------------------------------------------------ random draws
 
 def test_box_muller_normals(orc):
@@ -298,3 +314,57 @@ def test_proposal_draw_and_importance_correction(orc):
     est = (w[:, None] * xw).sum(0) / w.sum()
     ess = w.sum() ** 2 / (w * w).sum()
     assert np.all(np.abs(est - x0) < 4 * lim / np.sqrt(3 * ess)), (est, x0)
+
+
+# ------------------------------------------------------------------ learned-proposal label and map
+
+def test_cloud_moments_against_numpy(orc):
+    """The label of the learned proposal: numpy's weighted average and
+    weighted variance under the softmax of the log-weights, in units of the
+    limits about x0; invariant to a shift of every log-weight; uniform when
+    every weight is -inf; floored variance."""
+    rng = np.random.default_rng(21)
+    n = 300
+    x0 = np.array([0.1, -0.05, 0.02, 3.0, -2.0, 1.0])
+    L = np.array([0.3, 0.25, 0.2, 12.0, 10.0, 8.0])
+    x = x0 + L * rng.uniform(-1, 1, (n, 6))
+    lw = rng.normal(0, 4, n)
+    lw[rng.random(n) < 0.1] = -np.inf
+    w = np.exp(lw - lw.max())
+    m = np.average(x, axis=0, weights=w)
+    v = np.average((x - m) ** 2, axis=0, weights=w)
+    mean, var = orc.cloud_moments(lw, x, x0, L)
+    assert np.allclose(mean, (m - x0) / L, rtol=1e-12, atol=1e-14)
+    assert np.allclose(var, v / L ** 2, rtol=1e-11, atol=0)
+    mean2, var2 = orc.cloud_moments(lw + 123.5, x, x0, L)
+    assert np.allclose(mean2, mean, rtol=1e-12, atol=1e-14) and np.allclose(var2, var, rtol=1e-11)
+    mu, vu = orc.cloud_moments(np.full(n, -np.inf), x, x0, L)
+    assert np.allclose(mu, (x.mean(0) - x0) / L, atol=1e-13) and np.allclose(vu, x.var(0) / L ** 2, rtol=1e-11)
+    one = np.full(n, -np.inf)
+    one[17] = 0.0
+    m1, v1 = orc.cloud_moments(one, x, x0, L, var_floor=1e-4)
+    assert np.allclose(m1, (x[17] - x0) / L, atol=1e-14) and np.all(v1 == 1e-4)
+
+
+def test_proposal_from_network_closed_forms(orc):
+    """Zero outputs give the box centre and the variance var_scale L^2;
+    outputs are clipped (means to the box, log-variances to [-20, 2]); and
+    the network's own label format maps back to the cloud it summarises."""
+    x0 = np.array([0.1, -0.05, 0.02, 3.0, -2.0, 1.0])
+    L = np.array([0.3, 0.25, 0.2, 12.0, 10.0, 8.0])
+    m, lv = orc.proposal_from_network(np.zeros(12), x0, L, 4.0)
+    assert np.allclose(m, x0, atol=1e-15) and np.allclose(np.exp(lv), 4.0 * L ** 2, rtol=1e-14)
+    out = np.array([2.0, -3.0, 0.5, -0.25, 1.0, -1.0, 5.0, -30.0, 0.0, -1.0, 2.0, -20.0], np.float32)
+    m, lv = orc.proposal_from_network(out, x0, L, 1.0)
+    assert np.allclose(m, x0 + L * np.array([1.0, -1.0, 0.5, -0.25, 1.0, -1.0]), atol=1e-15)
+    assert np.allclose(lv - 2 * np.log(L), [2.0, -20.0, 0.0, -1.0, 2.0, -20.0], atol=1e-14)
+    rng = np.random.default_rng(5)
+    x = x0 + L * rng.uniform(-0.3, 0.3, (64, 6))
+    lw = rng.normal(0, 1, 64)
+    mean, var = orc.cloud_moments(lw, x, x0, L)
+    label = np.concatenate([mean, np.log(var)]).astype(np.float32)
+    m, lv = orc.proposal_from_network(label, x0, L, 1.0)
+    w = np.exp(lw - lw.max())
+    xm = np.average(x, axis=0, weights=w)
+    assert np.allclose(m, xm, rtol=1e-6, atol=1e-6 * L)
+    assert np.allclose(np.exp(lv), np.average((x - xm) ** 2, axis=0, weights=w), rtol=1e-6)
