@@ -227,14 +227,6 @@ __device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) 
 // The same with a constant b.
 __device__ __forceinline__ uint32_t mad_u24v(uint32_t a, uint32_t b, uint32_t c) { return __umul24(a, b) + c; }
 
-// floor(x + 0.5) as an integer in one instruction (x + 0.5 is exact for the
-// non-negative values below 2^22 it is given).
-__device__ __forceinline__ uint32_t round_half_up_u32(float x) {
-    int r;
-    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
-    return (uint32_t)r;
-}
-
 // ---------------------------------------------------------------- masks
 
 // Source byte: bit 0 = inside the source FOV, bit 1 = mask on (and in FOV).
@@ -695,10 +687,13 @@ __device__ __forceinline__ void image_body(const KArgs &a, uint32_t bx, uint32_t
                     const float y0 = fmaf(fya[p], x10 - x00, x00);
                     const float y1 = fmaf(fya[p], x11 - x01, x01);
                     const float sv = fmaf(fza[p], y1 - y0, y0);
-                    // s * 256 is exact, so one fused step equals the multiply-add;
-                    // the lerp layout's samples already carry the factor 256
+                    // s_fx = floor(fl(256 s + 0.5)): 256 s is exact, so one fused
+                    // step equals the multiply-add; the lerp layout's samples
+                    // already carry the factor 256 and take a separate FP32 add
+                    // (a rounding instruction that forms floor(x + 0.5) exactly
+                    // would differ where x + 0.5 rounds up to an integer)
                     const uint32_t sfx0 =
-                        LAYOUT == kLayoutLerp ? round_half_up_u32(sv) : (uint32_t)fmaf(sv, 256.0f, 0.5f);
+                        LAYOUT == kLayoutLerp ? (uint32_t)(sv + 0.5f) : (uint32_t)fmaf(sv, 256.0f, 0.5f);
                     const bool valid = in[p] & (okv[p] != 0u);
                     if constexpr (HIST) {
                         if (valid) {
