@@ -144,6 +144,23 @@ smc_status smc_trace(smc_ctx *ctx, double *score_k1, double *ess_k, double *est_
  * the MI score, which has no moments (use smc_score_particles). */
 smc_status smc_evaluate(smc_ctx *ctx, const double *states_n6, uint32_t n, int64_t *moments_n6);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: smc_evaluate
+ * on a DEVICE particle set (states_dev, n x 6 FP64) into DEVICE sums
+ * (moments_dev, n x 6 int64, same meaning as smc_evaluate's), asynchronous on
+ * the context's stream, calling no hipMalloc / hipFree.  The per-particle
+ * recipe words (48 bytes each) go to a library-wide device array of
+ * SMC_NOALLOC_MAX_PARTICLES particles (3 MiB, one per device, held until the
+ * process ends); the sums accumulate in moments_dev, which the call zeroes
+ * first.  Every call on a device shares that array: calls that overlap on one
+ * device (any context, any stream) race, so order them on one stream or
+ * synchronise between them.  Both buffers are caller-owned and must stay valid
+ * until the work completes; states are not checked for finiteness (non-finite
+ * states count no samples).  SMC_EINVAL for n > SMC_NOALLOC_MAX_PARTICLES,
+ * NULL pointers or the MI score; n == 0 does nothing. */
+#define SMC_NOALLOC_MAX_PARTICLES 65536u
+smc_status smc_evaluate_noalloc(smc_ctx *ctx, const double *states_dev, uint32_t n, int64_t *moments_dev);
+
 /* Exhaustive search (the EX baseline of Baseline and Evaluation Metrics):
  * score every point of the regular grid x_d = lo[d] + step[d] c_d,
  * c_d = 0 .. count[d] - 1 (axis 0 fastest), with the context's score, and

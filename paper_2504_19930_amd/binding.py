@@ -31,7 +31,8 @@ EXPORTS = ("smc_init", "smc_reset", "smc_step", "smc_estimate", "smc_get_particl
            "smc_batch_pair", "smc_batch_destroy", "smc_cnn_create", "smc_cnn_set_params", "smc_cnn_get_params",
            "smc_cnn_input", "smc_cnn_read_input", "smc_cnn_forward", "smc_cnn_backward", "smc_cnn_step", "smc_cnn_destroy",
            "smc_set_proposal", "smc_exhaustive", "smc_autotune", "smc_batch_autotune", "smc_set_frames",
-           "smc_score_particles", "smc_cloud_moments", "smc_set_proposal_from_network")
+           "smc_score_particles", "smc_cloud_moments", "smc_set_proposal_from_network",
+           "smc_evaluate_noalloc")
 
 
 class SmcError(RuntimeError):
@@ -74,6 +75,7 @@ def lib():
             "smc_get_particles": [vp, vp, vp, vp],
             "smc_trace": [vp, vp, vp, vp],
             "smc_evaluate": [vp, vp, u32, vp],
+            "smc_evaluate_noalloc": [vp, vp, u32, vp],
             "smc_set_particles": [vp, vp, u32],
             "smc_get_state": [vp, vp, P(C.c_size_t)],
             "smc_set_state": [vp, vp, C.c_size_t],
@@ -212,6 +214,18 @@ def smc_evaluate(ctx, states) -> np.ndarray:
     out = np.zeros((len(x), 6), np.int64)
     _check(lib().smc_evaluate(ctx, _ptr(x), len(x), _ptr(out)))
     return out
+
+
+NOALLOC_MAX_PARTICLES = 65536
+
+
+def smc_evaluate_noalloc(ctx, states_dev, moments_dev, n: int | None = None):
+    """Allocation-free evaluation on device tensors: states_dev (float64,
+    n x 6) and moments_dev (int64, n x 6) stay on the GPU; asynchronous on the
+    context's stream."""
+    n = len(states_dev) if n is None else int(n)
+    _check(lib().smc_evaluate_noalloc(ctx, C.c_void_p(states_dev.data_ptr()), n,
+                                      C.c_void_p(moments_dev.data_ptr())))
 
 
 def smc_set_particles(ctx, states, k_done: int):

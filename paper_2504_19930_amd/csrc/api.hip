@@ -115,6 +115,38 @@ Stats stats_from_sums(const unsigned long long s[4]) {
     return r;
 }
 
+// Allocation-free evaluation (smc_evaluate_noalloc): the recipe words of up
+// to SMC_NOALLOC_MAX_PARTICLES particles live in this file-scope device array
+// (one copy per device, for the life of the process).  Host code never uses
+// the array's name as an address: smc_init resolves, once per device and with
+// that device current, the device address of that device's copy, and the
+// entry point passes only that address to the kernels.
+static __device__ __align__(256) float scratch[12ull * SMC_NOALLOC_MAX_PARTICLES];
+
+std::mutex g_scratch_mu;
+std::map<int, float *> g_scratch_ptr;  // device ordinal -> address of its `scratch`
+
+// Resolve the current device's scratch address (no-op once resolved).
+smc_status resolve_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return SMC_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+        (void)hipGetLastError();
+        return fail(SMC_EDEVICE, "hipGetSymbolAddress of the evaluation scratch array failed on device %d: %s",
+                    device, hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = (float *)ptr;
+    return SMC_OK;
+}
+
+float *scratch_of(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+
 }  // namespace
 
 struct smc_ctx {
@@ -416,6 +448,10 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
         delete c;
         return fail(SMC_EDEVICE, "no HIP device");
     }
+    if ((st = resolve_scratch(c->device)) != SMC_OK) {
+        delete c;
+        return st;
+    }
     c->sn[0] = src->nx; c->sn[1] = src->ny; c->sn[2] = src->nz;
     c->tn[0] = tgt->nx; c->tn[1] = tgt->ny; c->tn[2] = tgt->nz;
     c->src = src->data;
@@ -585,6 +621,27 @@ smc_status smc_evaluate(smc_ctx *c, const double *states, uint32_t n, int64_t *m
     if (hipMemcpyAsync(moments, c->s_eval, 48ull * n, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
         return c->mark(fail(SMC_EDEVICE, "evaluation failed: %s", hipGetErrorString(hipGetLastError())));
+    return SMC_OK;
+}
+
+smc_status smc_evaluate_noalloc(smc_ctx *c, const double *states_dev, uint32_t n, int64_t *moments_dev) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (c->p.score == SMC_SCORE_MI) return fail(SMC_EINVAL, "the MI score has no moments");
+    if (n > SMC_NOALLOC_MAX_PARTICLES)
+        return fail(SMC_EINVAL, "n = %u exceeds the allocation-free maximum of %u particles", n,
+                    (unsigned)SMC_NOALLOC_MAX_PARTICLES);
+    if (n == 0) return SMC_OK;
+    if (!states_dev || !moments_dev) return fail(SMC_EINVAL, "states_dev and moments_dev must not be NULL");
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    float *words = scratch_of(c->device);
+    if (!words) return fail(SMC_EDEVICE, "no evaluation scratch resolved for device %d", c->device);
+    unsigned long long *sums = reinterpret_cast<unsigned long long *>(moments_dev);
+    // every word of particles 0 .. n-1 is rewritten; the sums start from zero
+    HIP_TRY(launch_words(states_dev, n, c->f.geom, c->f.nearest, words, c->stream));
+    HIP_TRY(launch_fill_u64(sums, 6ull * n, c->stream));
+    HIP_TRY(launch_score_frames(c, words, sums, nullptr, 0, n, false));
     return SMC_OK;
 }
 
