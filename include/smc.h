@@ -242,6 +242,19 @@ smc_status smc_get_tuning(smc_ctx *ctx, int32_t *layout, int32_t *particles_per_
  * NULL) receives that cost per launch.  Syncs. */
 smc_status smc_autotune(smc_ctx *ctx, uint32_t reps, double *best_ms);
 
+/* Measurement: how close the warp-and-score kernel runs to the cost of its
+ * source gathers alone (the warp-and-score path is bound by on-chip gather
+ * throughput; Implementation Details, full-resolution scoring).  On the
+ * context's current particle set -- the set (and estimate) its next
+ * iteration will score -- time (HIP events on the context's stream, one
+ * untimed launch then the mean of reps) a probe kernel that runs the same
+ * grid, culling, coordinates, offsets and source loads and nothing else, and
+ * the production kernel itself into a scratch sum buffer.  Leaves the filter
+ * state alone; must not overlap smc_step on the same context.  Outputs (ms
+ * per launch) may be NULL.  Syncs.  SMC_EINVAL for MI, multi-frame contexts,
+ * a target FOV, or a trilinear layout other than 3, 4 or 5. */
+smc_status smc_gather_probe(smc_ctx *ctx, uint32_t reps, double *probe_ms, double *score_ms);
+
 /* Kernel timing.  With enable != 0 every warp-and-score launch and every
  * filter launch of this context is bracketed by HIP events recorded on the
  * context's stream.  smc_profile_read syncs, returns the summed durations

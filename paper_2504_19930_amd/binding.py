@@ -32,7 +32,7 @@ EXPORTS = ("smc_init", "smc_reset", "smc_step", "smc_estimate", "smc_get_particl
            "smc_cnn_input", "smc_cnn_read_input", "smc_cnn_forward", "smc_cnn_backward", "smc_cnn_step", "smc_cnn_destroy",
            "smc_set_proposal", "smc_exhaustive", "smc_autotune", "smc_batch_autotune", "smc_set_frames",
            "smc_score_particles", "smc_cloud_moments", "smc_set_proposal_from_network",
-           "smc_evaluate_noalloc")
+           "smc_evaluate_noalloc", "smc_gather_probe")
 
 
 class SmcError(RuntimeError):
@@ -76,6 +76,7 @@ def lib():
             "smc_trace": [vp, vp, vp, vp],
             "smc_evaluate": [vp, vp, u32, vp],
             "smc_evaluate_noalloc": [vp, vp, u32, vp],
+            "smc_gather_probe": [vp, u32, vp, vp],
             "smc_set_particles": [vp, vp, u32],
             "smc_get_state": [vp, vp, P(C.c_size_t)],
             "smc_set_state": [vp, vp, C.c_size_t],
@@ -214,6 +215,12 @@ def smc_evaluate(ctx, states) -> np.ndarray:
     out = np.zeros((len(x), 6), np.int64)
     _check(lib().smc_evaluate(ctx, _ptr(x), len(x), _ptr(out)))
     return out
+
+
+def smc_gather_probe(ctx, reps: int = 1):
+    pm, sm = C.c_double(), C.c_double()
+    _check(lib().smc_gather_probe(ctx, int(reps), C.byref(pm), C.byref(sm)))
+    return pm.value, sm.value
 
 
 NOALLOC_MAX_PARTICLES = 65536
@@ -430,6 +437,10 @@ class Registration:
 
     def profile_read(self):
         return smc_profile_read(self.ctx)
+
+    def gather_probe(self, reps=1):
+        """(probe ms, production ms) per launch on the current particle set."""
+        return smc_gather_probe(self.ctx, reps)
 
     def close(self):
         if self.ctx:

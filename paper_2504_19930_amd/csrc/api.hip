@@ -178,6 +178,8 @@ struct smc_ctx {
     bool in_batch = false;
     smc_status sticky = SMC_OK;
     std::string sticky_msg;
+    // smc_gather_probe checksum word
+    uint32_t *probe_out = nullptr;
     // smc_evaluate workspace
     uint32_t eval_cap = 0;
     double *x_eval = nullptr;
@@ -642,6 +644,52 @@ smc_status smc_evaluate_noalloc(smc_ctx *c, const double *states_dev, uint32_t n
     HIP_TRY(launch_words(states_dev, n, c->f.geom, c->f.nearest, words, c->stream));
     HIP_TRY(launch_fill_u64(sums, 6ull * n, c->stream));
     HIP_TRY(launch_score_frames(c, words, sums, nullptr, 0, n, false));
+    return SMC_OK;
+}
+
+smc_status smc_gather_probe(smc_ctx *c, uint32_t reps, double *probe_ms, double *score_ms) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    if (reps < 1 || reps > 1000) return fail(SMC_EINVAL, "reps must be in 1..1000");
+    if (c->p.score == SMC_SCORE_MI || !c->frames.empty())
+        return fail(SMC_EINVAL, "the gather probe covers single-pair moment and mask scores");
+    smc_status st;
+    if ((st = c->check_sticky()) != SMC_OK) return st;
+    if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    const uint32_t np = c->f.n + 1;  // the particles and the estimate, as the filter scores them
+    const bool dispersed = c->k_done == 0 && c->prior_dispersed;
+    if ((st = ensure_eval(c, np)) != SMC_OK) return c->mark(st);
+    if (!c->probe_out && (st = c->alloc(&c->probe_out, 1)) != SMC_OK) return c->mark(st);
+    ScoreLaunch L = c->score_launch(c->f.words, c->s_eval, 0, np, true, dispersed);
+    if (!gather_probe_supported(L))
+        return fail(SMC_EINVAL, "no gather probe for this score mode, layout or target FOV");
+    hipEvent_t e0 = take_event(c), e1 = take_event(c);
+    if (!e0 || !e1) return fail(SMC_EDEVICE, "hipEventCreate failed");
+    // one untimed launch of each, then reps timed launches; the key is never
+    // matched (a checksum equal to it would only write probe_out)
+    double t_probe = 0.0, t_score = 0.0;
+    for (uint32_t r = 0; r <= reps; ++r) {
+        HIP_TRY(hipEventRecord(e0, c->stream));
+        HIP_TRY(launch_gather_probe(L, 0xA5A5A5A5u, c->probe_out, c->stream));
+        HIP_TRY(hipEventRecord(e1, c->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (r > 0) t_probe += ms;
+    }
+    for (uint32_t r = 0; r <= reps; ++r) {
+        HIP_TRY(launch_fill_u64(c->s_eval, 6ull * np, c->stream));
+        HIP_TRY(hipEventRecord(e0, c->stream));
+        HIP_TRY(launch_score(L, c->stream));
+        HIP_TRY(hipEventRecord(e1, c->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (r > 0) t_score += ms;
+    }
+    c->ev_pool.push_back(e0);
+    c->ev_pool.push_back(e1);
+    if (probe_ms) *probe_ms = t_probe / reps;
+    if (score_ms) *score_ms = t_score / reps;
     return SMC_OK;
 }
 

@@ -54,6 +54,10 @@ struct ScoreLaunch {
 };
 
 hipError_t launch_score(const ScoreLaunch &L, hipStream_t s);
+// Gather probe (measurement): the launch's grid, culling, coordinates and
+// source loads without the rest of the kernel's work; see score.hip.
+bool gather_probe_supported(const ScoreLaunch &L);
+hipError_t launch_gather_probe(const ScoreLaunch &L, uint32_t key, uint32_t *out, hipStream_t s);
 void score_grid(const ScoreLaunch &L, dim3 *grid, dim3 *block);
 bool score_pt_supported(int pt);
 // whether a packed trilinear layout can address a source of this shape

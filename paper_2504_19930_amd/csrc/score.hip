@@ -1150,4 +1150,143 @@ hipError_t launch_score(const ScoreLaunch &L, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- gather probe
+
+// Measurement kernels behind smc_gather_probe.  They run the grid, XCD order,
+// tile culling, coordinates, offsets and source loads of the warp-and-score
+// kernels exactly as those do, and replace everything else (target staging,
+// interpolation, fixed-point rounding, sums and their reduction) by an XOR of
+// the loaded words, so their time on a particle set is what the source
+// gathers alone cost on that set.  The checksum is stored only if it equals a
+// key the host never passes, which keeps every load live.
+namespace {
+
+template <int PT>
+__device__ __forceinline__ uint32_t probe_mask_body(const KArgs &a, uint32_t bx, uint32_t by) {
+    const Tile t = tile_of<PT>(a, bx, by);
+    const uint32_t live = live_mask<PT>(a, t, bx);
+    uint32_t chk = 0u;
+    if (live == 0u || !t.ok) return chk;
+    float mx[PT], my[PT], mz[PT], ax[PT], ay[PT], az[PT];
+    column_terms<PT>(a, t, mx, my, mz, ax, ay, az);
+    const uint32_t sn0 = (uint32_t)a.sn0, sn01 = (uint32_t)a.sn0 * (uint32_t)a.sn1;
+    const int nbytes = a.sn0 * a.sn1 * a.sn2;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(a.src), (short)0, nbytes, kBufferWord3);
+    const uint32_t nxb = __float_as_uint((float)a.sn0), nyb = __float_as_uint((float)a.sn1),
+                   nzb = __float_as_uint((float)a.sn2);
+    for (int k = t.k0; k < t.k1; ++k) {
+        const float fk = (float)k;
+        uint32_t off[PT];
+#pragma unroll
+        for (int p = 0; p < PT; ++p) {
+            const float ux = fmaf(ax[p], fk, mx[p]);
+            const float uy = fmaf(ay[p], fk, my[p]);
+            const float uz = fmaf(az[p], fk, mz[p]);
+            const bool in = ((live >> p) & 1u) & (__float_as_uint(ux) < nxb) & (__float_as_uint(uy) < nyb) &
+                            (__float_as_uint(uz) < nzb);
+            off[p] = mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, floor_u32(ux)));
+            off[p] = in ? off[p] : (uint32_t)nbytes;
+        }
+#pragma unroll
+        for (int p = 0; p < PT; ++p) chk ^= __builtin_amdgcn_raw_buffer_load_b8(rs, off[p], 0, 0);
+    }
+    return chk;
+}
+
+// Trilinear images in the one-gather layouts (octets, tiled octets, lerp
+// elements), the layouts the filter's launches use.
+template <int PT, int LAYOUT>
+__device__ __forceinline__ uint32_t probe_image_body(const KArgs &a, uint32_t bx, uint32_t by) {
+    const Tile t = tile_of<PT>(a, bx, by);
+    const uint32_t live = live_mask<PT>(a, t, bx);
+    uint32_t chk = 0u;
+    if (live == 0u || !t.ok) return chk;
+    float mx[PT], my[PT], mz[PT], ax[PT], ay[PT], az[PT];
+    column_terms<PT>(a, t, mx, my, mz, ax, ay, az);
+    constexpr uint32_t kElemShift = LAYOUT == kLayoutLerp ? 4u : 3u;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(a.src_packed), (short)0,
+                                                                        (int)a.src_bytes, kBufferWord3);
+    const uint32_t exb = __float_as_uint((float)(a.sn0 - 1)), eyb = __float_as_uint((float)(a.sn1 - 1)),
+                   ezb = __float_as_uint((float)(a.sn2 - 1));
+    for (int k = t.k0; k < t.k1; ++k) {
+        const float fk = (float)k;
+        uint32_t off[PT];
+#pragma unroll
+        for (int p = 0; p < PT; ++p) {
+            const float ux = fmaf(ax[p], fk, mx[p]);
+            const float uy = fmaf(ay[p], fk, my[p]);
+            const float uz = fmaf(az[p], fk, mz[p]);
+            const bool in = ((live >> p) & 1u) & (__float_as_uint(ux) <= exb) & (__float_as_uint(uy) <= eyb) &
+                            (__float_as_uint(uz) <= ezb);
+            const uint32_t ix = floor_u32(ux), iy = floor_u32(uy), iz = floor_u32(uz);
+            if (LAYOUT == kLayoutOctTile) {
+                uint32_t o = __mul24((int)(ix & 3u), -24) + (ix << 5);
+                o += __mul24((int)(iy & 3u), 32 - (int)a.ysb);
+                off[p] = o + __umul24(iy, a.ysb) + __umul24(iz, a.zsb);
+            } else {
+                off[p] = mad_u24(iz, a.zsb, mad_u24(iy, a.ysb, ix << kElemShift));
+            }
+            off[p] = in ? off[p] : a.src_bytes;
+        }
+#pragma unroll
+        for (int p = 0; p < PT; ++p) {
+            if constexpr (LAYOUT == kLayoutLerp) {
+                const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rs, off[p], 0, 0);
+                chk ^= w.x ^ w.y ^ w.z ^ w.w;
+            } else {
+                const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rs, off[p], 0, 0);
+                chk ^= w.x ^ w.y;
+            }
+        }
+    }
+    return chk;
+}
+
+template <int PT, int MODE, int LAYOUT>
+__global__ __launch_bounds__(kThreads) void k_gather_probe(const KArgs a, uint32_t key, uint32_t *out) {
+    uint32_t bx, by;
+    xcd_order(blockIdx.x, gridDim.x, (a.np + PT - 1) / PT, &bx, &by);
+    const uint32_t chk =
+        MODE == kModeMask ? probe_mask_body<PT>(a, bx, by) : probe_image_body<PT, LAYOUT>(a, bx, by);
+    if (chk == key) out[0] = chk;
+}
+
+template <int PT>
+ScoreKernel probe_kernel(const ScoreLaunch &L) {
+    typedef void (*PK)(const KArgs, uint32_t, uint32_t *);
+    PK k = nullptr;
+    if (L.mode == kModeMask) k = k_gather_probe<PT, kModeMask, kLayoutRaw>;
+    else if (L.mode == kModeImageTrilinear && L.layout == kLayoutOct)
+        k = k_gather_probe<PT, kModeImageTrilinear, kLayoutOct>;
+    else if (L.mode == kModeImageTrilinear && L.layout == kLayoutOctTile)
+        k = k_gather_probe<PT, kModeImageTrilinear, kLayoutOctTile>;
+    else if (L.mode == kModeImageTrilinear && L.layout == kLayoutLerp)
+        k = k_gather_probe<PT, kModeImageTrilinear, kLayoutLerp>;
+    return reinterpret_cast<ScoreKernel>(k);
+}
+
+}  // namespace
+
+bool gather_probe_supported(const ScoreLaunch &L) {
+    if (L.tgt_fov != nullptr || L.hist != nullptr) return false;
+    if (L.mode == kModeMask) return true;
+    return L.mode == kModeImageTrilinear &&
+           (L.layout == kLayoutOct || L.layout == kLayoutOctTile || L.layout == kLayoutLerp);
+}
+
+hipError_t launch_gather_probe(const ScoreLaunch &L, uint32_t key, uint32_t *out, hipStream_t s) {
+    if (!gather_probe_supported(L)) return hipErrorInvalidValue;
+    if (L.np == 0) return hipSuccess;
+    int chunks;
+    const int pt = score_pt_supported(L.pt) ? L.pt : 8;
+    const KArgs a = make_args(L, pt, &chunks);
+    dim3 grid, block;
+    score_grid(L, &grid, &block);
+    ScoreKernel k = pt == 4 ? probe_kernel<4>(L) : (pt == 16 ? probe_kernel<16>(L) : probe_kernel<8>(L));
+    typedef void (*PK)(const KArgs, uint32_t, uint32_t *);
+    hipLaunchKernelGGL(reinterpret_cast<PK>(k), grid, block, 0, s, a, key, out);
+    return hipGetLastError();
+}
+
 }  // namespace smc

@@ -419,7 +419,8 @@ def test_batch_pairs_equal_single_runs_across_replays(smc, orc):
     """Uneven pairs (mask and trilinear image, different sizes, particle and
     iteration counts) in one graph launch: every pair equals its own
     single-context run bit for bit, on several replays with new seeds and
-    eager work in between; one mask pair also against the oracle."""
+    eager work in between; one mask pair and one trilinear image pair also
+    against the oracle."""
     specs = [("mask", 40, 96, 4), ("image", 33, 64, 3), ("mask", 28, 33, 5), ("image", 45, 130, 4),
              ("mask", 52, 17, 2), ("image", 24, 40, 5)]
     pairs, host = [], []
@@ -452,6 +453,13 @@ def test_batch_pairs_equal_single_runs_across_replays(smc, orc):
         o = orc.smc_run(pr["src"], pr["tgt"], dict(prm, seed=seeds[0]))
         assert np.array_equal(b.particles(0)["ancestors"], o["ancestors"])
         _assert_final_close(orc, b.estimate(0)["params"], o["est"])
+        # a trilinear image pair (NCC, source FOV) of the batch against the oracle too
+        pr, prm = host[1]
+        o = orc.smc_run(orc.Volume(pr["src"], fov=pr["src_fov"]), orc.Volume(pr["tgt"]), dict(prm, seed=seeds[1]))
+        assert np.array_equal(b.particles(1)["ancestors"], o["ancestors"])
+        assert np.allclose(b.particles(1)["states"], o["states"], rtol=0, atol=1e-12)
+        assert np.allclose(b.trace(1)["score"], o["trace_score"], rtol=0, atol=1e-12)
+        _assert_final_close(orc, b.estimate(1)["params"], o["est"])
     b.close()
 
 
