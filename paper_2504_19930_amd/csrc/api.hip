@@ -157,6 +157,7 @@ struct smc_ctx {
     int32_t sn[3] = {0, 0, 0}, tn[3] = {0, 0, 0};
     const uint8_t *src = nullptr, *src_fov = nullptr, *tgt = nullptr, *tgt_fov = nullptr;
     uint8_t *src_prep = nullptr, *tgt_prep = nullptr, *src_ok = nullptr;
+    uint32_t *src_bits = nullptr;  // masks: bitmap of the source's on bits
     int layout = kDefaultLayout, pt = kDefaultPT, zchunk = kDefaultZChunkMask;
     int32_t box_lo[3] = {1, 1, 1}, box_hi[3] = {-1, -1, -1};  // source mask bounding box (empty)
     void *packed[kLayouts] = {};
@@ -229,6 +230,7 @@ struct smc_ctx {
         }
         if (mode == kModeMask) {
             L.src = src_prep;
+            L.src_bits = src_bits;
             L.src_ok = nullptr;
             L.tgt = tgt_prep;
             L.tgt_fov = nullptr;
@@ -476,8 +478,10 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
     if (c->mode == kModeMask) {
         if ((st = c->alloc(&c->src_prep, vs)) != SMC_OK) return bail(st);
         if ((st = c->alloc(&c->tgt_prep, vt)) != SMC_OK) return bail(st);
+        if ((st = c->alloc((uint8_t **)&c->src_bits, mask_bits_bytes(c->sn))) != SMC_OK) return bail(st);
         if (launch_prep_mask(src->data, src->fov, c->src_prep, vs, c->stream) != hipSuccess ||
-            launch_prep_mask(tgt->data, tgt->fov, c->tgt_prep, vt, c->stream) != hipSuccess)
+            launch_prep_mask(tgt->data, tgt->fov, c->tgt_prep, vt, c->stream) != hipSuccess ||
+            launch_pack_mask_bits(c->src_prep, c->sn, c->src_bits, c->stream) != hipSuccess)
             return bail(fail(SMC_EDEVICE, "mask preparation launch failed"));
     } else if (src->fov) {
         if (c->mode == kModeImageTrilinear) {
@@ -1267,6 +1271,8 @@ smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode, int vmode) {
     for (uint32_t q = 0; q < n; ++q) {
         smc_ctx *c = b->pairs[C.members[q]];
         ScoreLaunch L = c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true);
+        // the persistent mask launch reads every pair's source bitmap
+        if (mode == kModeMask && !L.src_bits) return fail(SMC_EINVAL, "mask pair %u has no source bitmap", C.members[q]);
         if (q == 0) {
             pt = L.pt;
             layout = L.layout;

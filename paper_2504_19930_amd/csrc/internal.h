@@ -41,6 +41,7 @@ struct ScoreLaunch {
     // n and b_ov then count only the tiles that reach it)
     bool cull_box;
     int32_t box_lo[3], box_hi[3];
+    const uint32_t *src_bits = nullptr;  // mask: bitmap of the source's on bits (the filter's launches)
     const uint8_t *src_ok;    // image: corner-valid bytes (source FOV) or nullptr
     const uint8_t *tgt;       // mask: prepared bits; image: intensities
     const uint8_t *tgt_fov;   // image: target FOV or nullptr
@@ -105,6 +106,10 @@ hipError_t launch_prep_mask(const uint8_t *vol, const uint8_t *fov, uint8_t *out
 // Bounding box of the voxels with bit 1 set (mask on): out = {min x, y, z, max x, y, z};
 // initialise out to {INT_MAX x3, -1 x3}.
 hipError_t launch_mask_bbox(const uint8_t *prep, const int32_t n[3], int32_t *out, hipStream_t s);
+// Bitmap of the prepared source mask's "on" bits (rows padded to 32 bits):
+// bytes of the bitmap of a volume of shape n, and the packing launch.
+uint64_t mask_bits_bytes(const int32_t n[3]);
+hipError_t launch_pack_mask_bits(const uint8_t *prep, const int32_t n[3], uint32_t *out, hipStream_t s);
 hipError_t launch_corner_valid(const uint8_t *fov, uint8_t *out, const int32_t n[3], hipStream_t s);
 // out[0..3] += (fov count, nonzero count, sum v, sum v^2) over the FOV
 hipError_t launch_volume_sums(const uint8_t *vol, const uint8_t *fov, int64_t n, unsigned long long *out,

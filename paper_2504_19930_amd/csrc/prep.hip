@@ -18,6 +18,22 @@ __global__ void k_prep_mask(const uint8_t *vol, const uint8_t *fov, uint8_t *out
     }
 }
 
+// Source mask as a bitmap for the filter's mask launches: bit x % 32 of
+// dword (x / 32) + W (y + ny z), W = ceil(nx / 32), is set iff the prepared
+// byte has its "on" bit (on and inside the source FOV); pad bits are zero.
+__global__ void k_pack_mask_bits(const uint8_t *prep, int32_t nx, int32_t ny, int32_t nz, uint32_t W,
+                                 uint32_t *out) {
+    const int64_t n = (int64_t)W * ny * nz;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = q / W;
+        const int32_t x0 = (int32_t)(q - row * W) * 32;
+        const uint8_t *r = prep + row * (int64_t)nx;
+        uint32_t w = 0u;
+        for (int b = 0; b < 32 && x0 + b < nx; ++b) w |= ((uint32_t)(r[x0 + b] >> 1) & 1u) << b;
+        out[q] = w;
+    }
+}
+
 // A trilinear sample with base corner (i, j, k) is valid iff all eight
 // (edge-clamped) corners are inside the FOV.
 __global__ void k_corner_valid(const uint8_t *fov, uint8_t *out, int32_t nx, int32_t ny, int32_t nz) {
@@ -202,6 +218,17 @@ unsigned blocks_for(int64_t n) {
 
 hipError_t launch_prep_mask(const uint8_t *vol, const uint8_t *fov, uint8_t *out, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_prep_mask, dim3(blocks_for(n)), dim3(256), 0, s, vol, fov, out, n);
+    return hipGetLastError();
+}
+
+uint64_t mask_bits_bytes(const int32_t n[3]) {
+    return 4ull * (uint64_t)((n[0] + 31) / 32) * (uint64_t)n[1] * (uint64_t)n[2];
+}
+
+hipError_t launch_pack_mask_bits(const uint8_t *prep, const int32_t n[3], uint32_t *out, hipStream_t s) {
+    const uint32_t W = (uint32_t)((n[0] + 31) / 32);
+    const int64_t tot = (int64_t)W * n[1] * n[2];
+    hipLaunchKernelGGL(k_pack_mask_bits, dim3(blocks_for(tot)), dim3(256), 0, s, prep, n[0], n[1], n[2], W, out);
     return hipGetLastError();
 }
 

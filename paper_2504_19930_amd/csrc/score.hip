@@ -28,6 +28,7 @@ constexpr int kTY = 8;
 constexpr int kThreads = kTX * kTY;
 constexpr int kWX = 16;  // wave patch width (x); 64 / kWX rows
 static_assert(kTX % kWX == 0 && 64 % kWX == 0 && kTY % (64 / kWX) == 0, "waves must tile the 32 x 8 column");
+static_assert(kWX == 16, "a wave's four quarters are 4 x 4 squares side by side in x");
 constexpr int kWaves = kThreads / 64;
 constexpr int kZChunkMax = 256;  // keeps every per-thread 32-bit sum below 2^32
 constexpr int kSlab = 32;        // target slices staged in LDS at a time
@@ -104,13 +105,16 @@ __device__ __forceinline__ Tile tile_of(const KArgs &a, uint32_t bx, uint32_t by
     b -= zc * tiles;
     const int ty = b / a.tiles_x;
     const int tx = b - ty * a.tiles_x;
-    // each wave covers a kWX x (64 / kWX) patch of the tile: a squarer patch
-    // maps to fewer source cache lines under rotation
+    // each wave covers a kWX x (64 / kWX) patch of the tile, and each quarter
+    // of the wave (16 lanes, which the texture path serves together) a 4 x 4
+    // square of it: a gather costs about one cycle per cache line that a
+    // quarter touches, and a square's rotated image spans fewer source rows
+    // and slices than a 16-voxel row's
     const int lane = (int)(threadIdx.x % 64), wave = (int)(threadIdx.x / 64);
     t.x0 = tx * kTX;
     t.y0 = ty * kTY;
-    t.i = t.x0 + (wave % (kTX / kWX)) * kWX + lane % kWX;
-    t.j = t.y0 + (wave / (kTX / kWX)) * (64 / kWX) + lane / kWX;
+    t.i = t.x0 + (wave % (kTX / kWX)) * kWX + (lane / 16) * 4 + lane % 4;
+    t.j = t.y0 + (wave / (kTX / kWX)) * (64 / kWX) + (lane % 16) / 4;
     t.ok = t.i < a.tn0 && t.j < a.tn1;
     t.k0 = zc * a.zchunk;
     t.k1 = min(t.k0 + a.zchunk, a.tn2);
@@ -233,8 +237,13 @@ __device__ __forceinline__ uint32_t mad_u24v(uint32_t a, uint32_t b, uint32_t c)
 // Target byte: bit 0 = inside the target FOV, bit 1 = mask on (and in FOV).
 // Per particle two packed counters: acc1 = n | a << 16, acc2 = b_ov | c << 16
 // (each half counts at most one voxel per z step, and a z-chunk < 2^16).
-// AC: only a and c (what Dice uses; the filter's launches), as twice the
-// counts: acc1 = 2 a, acc2 = 2 c; n and b_ov are left at zero.
+// AC: only a and c (what Dice uses; the filter's launches), from the source
+// bitmap (one bit per voxel, the "on" bit; rows of ceil(nx / 32) dwords):
+// the sample is bit x % 32 of a dword, and one packed counter per particle
+// takes a + 2^16 c as bit * (in-FOV + 2^16 on) of the target voxel.  The
+// bitmap puts the rows of a slice 4 ceil(nx / 32) bytes apart, so the rotated
+// footprint of a wave's samples spans a few cache lines instead of one or two
+// per source row and slice as with a byte per voxel.
 template <int PT, bool AC = false>
 __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t by) {
     const Tile t = tile_of<PT>(a, bx, by);
@@ -254,10 +263,11 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
     {
         // prepared source bytes through a bounds-checked buffer with 32-bit
         // offsets: an outside sample may form any offset, its result is masked
-        const uint32_t sn0 = (uint32_t)a.sn0, sn01 = (uint32_t)a.sn0 * (uint32_t)a.sn1;
-        const int nbytes = a.sn0 * a.sn1 * a.sn2;
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(a.src), (short)0, nbytes, kBufferWord3);
+        const uint32_t sn0 = AC ? a.ysb : (uint32_t)a.sn0, sn01 = AC ? a.zsb : (uint32_t)a.sn0 * (uint32_t)a.sn1;
+        const int nbytes = AC ? (int)a.src_bytes : a.sn0 * a.sn1 * a.sn2;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            AC ? const_cast<void *>(a.src_packed) : (void *)const_cast<uint8_t *>(a.src), (short)0, nbytes,
+            kBufferWord3);
         // nearest (the words carry +0.5): inside iff 0 <= u < n, one unsigned
         // compare of bit patterns per axis (coordinates are never -0)
         const uint32_t nxb = __float_as_uint((float)a.sn0), nyb = __float_as_uint((float)a.sn1),
@@ -277,11 +287,12 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
                 const uint32_t tb = tslab8[(uint32_t)(k - kb) * kThreads + col];
                 const uint32_t keep = (tb & 1u) ? 3u : 0u;
                 const bool ton = (tb & 2u) != 0u;
-                // AC: the on bit (2) where the target voxel is in its FOV / on
-                const uint32_t ka = tb & 1u ? 2u : 0u, kc = tb & 2u;
+                // AC: a source bit adds 1 to a where the target voxel is in its
+                // FOV and 2^16 to c where it is on (bit 1 implies bit 0)
+                const uint32_t tmul = (tb & 1u) + ((tb & 2u) << 15);
                 const float fk = (float)k;
                 // offsets of all PT samples first, then every load, then the sums
-                uint32_t off[PT];
+                uint32_t off[PT], ix[PT];
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
                     const float ux = fmaf(ax[p], fk, mx[p]);
@@ -293,17 +304,25 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
                     // outside samples (and particles culled for this tile) load
                     // from the buffer's end: zero, no cache lines touched, so they
                     // count nothing
-                    off[p] = mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, floor_u32(ux)));
+                    if constexpr (AC) {
+                        // byte offset of dword x / 32 of the row; the bit index is
+                        // x % 32 (the low five bits of the offset operand)
+                        ix[p] = floor_u32(ux);
+                        off[p] = mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, (ix[p] >> 3) & ~3u));
+                    } else {
+                        off[p] = mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, floor_u32(ux)));
+                    }
                     off[p] = in ? off[p] : nbytes;
                 }
                 uint32_t val[PT];
 #pragma unroll
-                for (int p = 0; p < PT; ++p) val[p] = __builtin_amdgcn_raw_buffer_load_b8(rs, off[p], 0, 0);
+                for (int p = 0; p < PT; ++p)
+                    val[p] = AC ? __builtin_amdgcn_raw_buffer_load_b32(rs, off[p], 0, 0)
+                                : __builtin_amdgcn_raw_buffer_load_b8(rs, off[p], 0, 0);
 #pragma unroll
                 for (int p = 0; p < PT; ++p) {
                     if constexpr (AC) {
-                        acc1[p] += val[p] & ka;
-                        acc2[p] += val[p] & kc;
+                        acc1[p] = mad_u24v(__builtin_amdgcn_ubfe(val[p], ix[p], 1u), tmul, acc1[p]);
                     } else {
                         // v in 0..3 (bit 0 in both FOVs, bit 1 also on); inc = (v & 1) +
                         // (v >> 1) 2^16 = v + (v >> 1) (2^16 - 2)
@@ -320,10 +339,12 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
+        // AC: a wave's halves stay below 64 x 256 < 2^16, so one sum serves both
+        const uint32_t ac = AC ? wave_sum(acc1[p]) : 0u;
         const uint32_t n = AC ? 0u : wave_sum(acc1[p] & 0xFFFFu);
-        const uint32_t aa = AC ? wave_sum(acc1[p]) >> 1 : wave_sum(acc1[p] >> 16);
+        const uint32_t aa = AC ? ac & 0xFFFFu : wave_sum(acc1[p] >> 16);
         const uint32_t b = AC ? 0u : wave_sum(acc2[p] & 0xFFFFu);
-        const uint32_t c = AC ? wave_sum(acc2[p]) >> 1 : wave_sum(acc2[p] >> 16);
+        const uint32_t c = AC ? ac >> 16 : wave_sum(acc2[p] >> 16);
         if (lane == 0) {
             red[wave][p][0] = n;
             red[wave][p][1] = aa;
@@ -989,6 +1010,17 @@ KArgs make_args(const ScoreLaunch &L, int pt, int *nz_chunks) {
             a.cull_hi[d] = (float)L.sn[d];
         }
     }
+    if (L.mode == kModeMask) {
+        // the filter's launches read the source bitmap: byte strides of its
+        // rows and slices (zero without a bitmap; those launches use bytes)
+        const uint32_t row = 4u * (uint32_t)((L.sn[0] + 31) / 32);
+        a.src_packed = L.src_bits;
+        a.src_bytes = L.src_bits ? (uint32_t)mask_bits_bytes(L.sn) : 0u;
+        a.ysb = row;
+        a.zsb = row * (uint32_t)L.sn[1];
+        *nz_chunks = chunks;
+        return a;
+    }
     const uint32_t eb = (uint32_t)packed_bytes_per_voxel(L.layout);
     a.src_bytes = (uint32_t)std::min<uint64_t>(packed_bytes(L.layout, L.sn), 0xFFFFFFFFull);
     if (L.layout == kLayoutOctTile) {
@@ -1027,7 +1059,7 @@ ScoreKernel pick_tri_layout(int layout, int vmode) {
 
 template <int PT>
 ScoreKernel pick(const ScoreLaunch &L) {
-    if (L.mode == kModeMask) return L.cull_box ? k_score_mask<PT, true> : k_score_mask<PT, false>;
+    if (L.mode == kModeMask) return L.cull_box && L.src_bits ? k_score_mask<PT, true> : k_score_mask<PT, false>;
     const bool sok = L.src_ok != nullptr;
     if (L.mode == kModeImageNearest)
         return sok ? k_score_image<PT, kLayoutRaw, false, 1> : k_score_image<PT, kLayoutRaw, false, 0>;
@@ -1161,7 +1193,7 @@ hipError_t launch_score(const ScoreLaunch &L, hipStream_t s) {
 // key the host never passes, which keeps every load live.
 namespace {
 
-template <int PT>
+template <int PT, bool AC>
 __device__ __forceinline__ uint32_t probe_mask_body(const KArgs &a, uint32_t bx, uint32_t by) {
     const Tile t = tile_of<PT>(a, bx, by);
     const uint32_t live = live_mask<PT>(a, t, bx);
@@ -1169,10 +1201,11 @@ __device__ __forceinline__ uint32_t probe_mask_body(const KArgs &a, uint32_t bx,
     if (live == 0u || !t.ok) return chk;
     float mx[PT], my[PT], mz[PT], ax[PT], ay[PT], az[PT];
     column_terms<PT>(a, t, mx, my, mz, ax, ay, az);
-    const uint32_t sn0 = (uint32_t)a.sn0, sn01 = (uint32_t)a.sn0 * (uint32_t)a.sn1;
-    const int nbytes = a.sn0 * a.sn1 * a.sn2;
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(a.src), (short)0, nbytes, kBufferWord3);
+    const uint32_t sn0 = AC ? a.ysb : (uint32_t)a.sn0, sn01 = AC ? a.zsb : (uint32_t)a.sn0 * (uint32_t)a.sn1;
+    const int nbytes = AC ? (int)a.src_bytes : a.sn0 * a.sn1 * a.sn2;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        AC ? const_cast<void *>(a.src_packed) : (void *)const_cast<uint8_t *>(a.src), (short)0, nbytes,
+        kBufferWord3);
     const uint32_t nxb = __float_as_uint((float)a.sn0), nyb = __float_as_uint((float)a.sn1),
                    nzb = __float_as_uint((float)a.sn2);
     for (int k = t.k0; k < t.k1; ++k) {
@@ -1185,11 +1218,14 @@ __device__ __forceinline__ uint32_t probe_mask_body(const KArgs &a, uint32_t bx,
             const float uz = fmaf(az[p], fk, mz[p]);
             const bool in = ((live >> p) & 1u) & (__float_as_uint(ux) < nxb) & (__float_as_uint(uy) < nyb) &
                             (__float_as_uint(uz) < nzb);
-            off[p] = mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, floor_u32(ux)));
+            const uint32_t xo = AC ? (floor_u32(ux) >> 3) & ~3u : floor_u32(ux);
+            off[p] = mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, xo));
             off[p] = in ? off[p] : (uint32_t)nbytes;
         }
 #pragma unroll
-        for (int p = 0; p < PT; ++p) chk ^= __builtin_amdgcn_raw_buffer_load_b8(rs, off[p], 0, 0);
+        for (int p = 0; p < PT; ++p)
+            chk ^= AC ? __builtin_amdgcn_raw_buffer_load_b32(rs, off[p], 0, 0)
+                      : __builtin_amdgcn_raw_buffer_load_b8(rs, off[p], 0, 0);
     }
     return chk;
 }
@@ -1243,12 +1279,12 @@ __device__ __forceinline__ uint32_t probe_image_body(const KArgs &a, uint32_t bx
     return chk;
 }
 
-template <int PT, int MODE, int LAYOUT>
+template <int PT, int MODE, int LAYOUT, bool AC = false>
 __global__ __launch_bounds__(kThreads) void k_gather_probe(const KArgs a, uint32_t key, uint32_t *out) {
     uint32_t bx, by;
     xcd_order(blockIdx.x, gridDim.x, (a.np + PT - 1) / PT, &bx, &by);
     const uint32_t chk =
-        MODE == kModeMask ? probe_mask_body<PT>(a, bx, by) : probe_image_body<PT, LAYOUT>(a, bx, by);
+        MODE == kModeMask ? probe_mask_body<PT, AC>(a, bx, by) : probe_image_body<PT, LAYOUT>(a, bx, by);
     if (chk == key) out[0] = chk;
 }
 
@@ -1256,7 +1292,9 @@ template <int PT>
 ScoreKernel probe_kernel(const ScoreLaunch &L) {
     typedef void (*PK)(const KArgs, uint32_t, uint32_t *);
     PK k = nullptr;
-    if (L.mode == kModeMask) k = k_gather_probe<PT, kModeMask, kLayoutRaw>;
+    if (L.mode == kModeMask)
+        k = L.cull_box && L.src_bits ? k_gather_probe<PT, kModeMask, kLayoutRaw, true>
+                                     : k_gather_probe<PT, kModeMask, kLayoutRaw, false>;
     else if (L.mode == kModeImageTrilinear && L.layout == kLayoutOct)
         k = k_gather_probe<PT, kModeImageTrilinear, kLayoutOct>;
     else if (L.mode == kModeImageTrilinear && L.layout == kLayoutOctTile)
