@@ -236,6 +236,9 @@ def lv224(inp, args):
     N, K = prm["n_particles"], prm["n_iters"]
     V = int(lv["tgt_masks"][0].size)
     reg = binding.Registration(dev(lv["src_masks"][0]), dev(lv["tgt_masks"][0]), prm)
+    if args.mask_tuning:
+        ppg, depth = (int(v) for v in args.mask_tuning.split(","))
+        reg.tune(None, ppg, depth)
     sm, ss = dev(lv["src_masks"]), dev(lv["src_speckle"])
     F = len(lv["src_masks"])
     out_m = torch.empty_like(sm)
@@ -497,6 +500,8 @@ def main():
     ap.add_argument("--no-speckle", action="store_true", help="skip the nested speckle160 line")
     ap.add_argument("--speckle-steps", type=int, default=3)
     ap.add_argument("--no-gather-probe", action="store_true")
+    ap.add_argument("--mask-tuning", default=None,
+                    help="particles_per_group,tile_depth of the lv224 mask launch (default: the library's)")
     ap.add_argument("--image-tuning", default=DEFAULT_IMAGE_TUNING,
                     help="layout,particles_per_group,tile_depth of the speckle160 warp-and-score launch")
     ap.add_argument("--lv-frames", type=int, default=LV_FRAMES,

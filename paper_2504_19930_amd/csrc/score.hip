@@ -145,17 +145,25 @@ __device__ __forceinline__ void column_terms(const KArgs &a, const Tile &t, floa
 }
 
 // Bit p set iff particle p's image of this tile (the box of target voxels
-// [i0, i1] x [j0, j1] x [k0, k1 - 1], mapped by the affine recipe, whose
-// extremes sit at the box corners) meets the cull box.  Uniform across the
-// workgroup.
+// [i0, i1] x [j0, j1] x [k0, k1 - 1], mapped by the affine recipe) meets the
+// cull box.  The image of a box under an affine map is bounded per axis by
+// the image of its centre plus or minus sum_e |A_de| h_e (h the box's half
+// extents); both are formed in FP32, whose rounding (a few ulps of values
+// below 2^16) stays far inside the margin, so a tile is skipped only if no
+// sample of it can land in the box.  Uniform across the workgroup.
 template <int PT>
 __device__ __forceinline__ uint32_t live_mask(const KArgs &a, const Tile &t, uint32_t bx) {
     const int tiles = a.tiles_x * a.tiles_y;
     const int b = (int)bx % tiles;
     const int ty = b / a.tiles_x, tx = b - ty * a.tiles_x;
-    const float lo[3] = {(float)(tx * kTX), (float)(ty * kTY), (float)t.k0};
-    const float hi[3] = {(float)min(tx * kTX + kTX - 1, a.tn0 - 1), (float)min(ty * kTY + kTY - 1, a.tn1 - 1),
-                         (float)(t.k1 - 1)};
+    const int lo[3] = {tx * kTX, ty * kTY, t.k0};
+    const int hi[3] = {min(tx * kTX + kTX - 1, a.tn0 - 1), min(ty * kTY + kTY - 1, a.tn1 - 1), t.k1 - 1};
+    float c[3], h[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        c[e] = 0.5f * (float)(lo[e] + hi[e]);
+        h[e] = 0.5f * (float)(hi[e] - lo[e]);
+    }
     const uint32_t last = a.p0 + a.np - 1;
     uint32_t live = 0;
 #pragma unroll
@@ -164,14 +172,10 @@ __device__ __forceinline__ uint32_t live_mask(const KArgs &a, const Tile &t, uin
         bool ok = p < t.npg;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            float umin = w[4 * d + 3], umax = w[4 * d + 3];
-#pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                const float c0 = w[4 * d + e] * lo[e], c1 = w[4 * d + e] * hi[e];
-                umin += fminf(c0, c1);
-                umax += fmaxf(c0, c1);
-            }
-            ok = ok && umax + kCullMargin >= a.cull_lo[d] && umin - kCullMargin <= a.cull_hi[d];
+            const float uc = fmaf(w[4 * d + 2], c[2], fmaf(w[4 * d + 1], c[1], fmaf(w[4 * d], c[0], w[4 * d + 3])));
+            const float r = fmaf(fabsf(w[4 * d + 2]), h[2], fmaf(fabsf(w[4 * d + 1]), h[1], fabsf(w[4 * d]) * h[0])) +
+                            kCullMargin;
+            ok = ok && uc + r >= a.cull_lo[d] && uc - r <= a.cull_hi[d];
         }
         live |= ok ? (1u << p) : 0u;
     }
