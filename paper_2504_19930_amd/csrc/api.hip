@@ -181,6 +181,10 @@ struct smc_ctx {
     std::string sticky_msg;
     // smc_gather_probe checksum word
     uint32_t *probe_out = nullptr;
+    // masks: culled item lists of the filter's launches (capacity item_cap)
+    void *items = nullptr;
+    uint32_t *item_counters = nullptr;
+    uint64_t item_cap = 0;
     // smc_evaluate workspace
     uint32_t eval_cap = 0;
     double *x_eval = nullptr;
@@ -253,6 +257,9 @@ struct smc_ctx {
         }
         L.p0 = p0;
         L.np = np;
+        L.items = items;
+        L.item_counters = item_counters;
+        L.item_cap = item_cap;
         return L;
     }
 
@@ -365,6 +372,28 @@ smc_status launch_prior(smc_ctx *c) {
     HIP_TRY(launch_init_particles(c->f, c->stream));
     c->k_done = 0;
     c->prior_dispersed = !c->f.has_proposal;
+    return SMC_OK;
+}
+
+// Mask contexts: item lists large enough for a filter launch (N + 1
+// particles) under the current tuning; smaller buffers are freed.
+smc_status ensure_items(smc_ctx *c) {
+    if (c->mode != kModeMask) return SMC_OK;
+    smc_status st;
+    if (!c->item_counters && (st = c->alloc(&c->item_counters, kItemCounterWords)) != SMC_OK) return st;
+    const uint64_t need = score_items_for(c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true));
+    if (need <= c->item_cap) return SMC_OK;
+    if (c->items) {
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(SMC_EDEVICE, "stream sync failed");
+        c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), c->items), c->allocs.end());
+        (void)hipFree(c->items);
+        c->items = nullptr;
+        c->item_cap = 0;
+    }
+    uint2 *buf = nullptr;
+    if ((st = c->alloc(&buf, need)) != SMC_OK) return st;
+    c->items = buf;
+    c->item_cap = need;
     return SMC_OK;
 }
 
@@ -571,6 +600,7 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
         if (launch_fill_u64((unsigned long long *)c->hist, words / 2, c->stream) != hipSuccess)
             return bail(fail(SMC_EDEVICE, "histogram clear failed"));
     }
+    if ((st = ensure_items(c)) != SMC_OK) return bail(st);
     if ((st = launch_prior(c)) != SMC_OK) return bail(st);
     *out = c;
     return SMC_OK;
@@ -987,6 +1017,7 @@ smc_status smc_set_tuning(smc_ctx *c, int32_t layout, int32_t pt, int32_t tile_d
         if ((st = smc_set_tuning(fr, layout, pt, tile_depth)) != SMC_OK) return c->mark(st);
     if (pt >= 0) c->pt = pt;
     if (tile_depth > 0) c->zchunk = tile_depth;
+    if ((st = ensure_items(c)) != SMC_OK) return c->mark(st);
     return SMC_OK;
 }
 

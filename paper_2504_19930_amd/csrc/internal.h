@@ -52,7 +52,16 @@ struct ScoreLaunch {
     // mutual information: the launch adds into kMiBins^2 counts per particle
     // (indexed like words) instead of the moments
     uint32_t *hist = nullptr;
+    // masks, the filter's launches: the culled item lists (capacity item_cap
+    // items of 8 bytes) and their counters (kItemCounterWords 32-bit words);
+    // launches with more items than item_cap use a grid of one workgroup per item
+    void *items = nullptr;
+    uint32_t *item_counters = nullptr;
+    uint64_t item_cap = 0;
 };
+constexpr uint32_t kItemCounterWords = 512;
+// Items (tiles x particle groups) of a launch of L's shape with np particles.
+uint64_t score_items_for(const ScoreLaunch &L);
 
 hipError_t launch_score(const ScoreLaunch &L, hipStream_t s);
 // Gather probe (measurement): the launch's grid, culling, coordinates and

@@ -144,13 +144,38 @@ __device__ __forceinline__ void column_terms(const KArgs &a, const Tile &t, floa
     }
 }
 
-// Bit p set iff particle p's image of this tile (the box of target voxels
+// Culling.  live_mask: bit p set iff particle p's image of this tile (the box of target voxels
 // [i0, i1] x [j0, j1] x [k0, k1 - 1], mapped by the affine recipe) meets the
 // cull box.  The image of a box under an affine map is bounded per axis by
 // the image of its centre plus or minus sum_e |A_de| h_e (h the box's half
 // extents); both are formed in FP32, whose rounding (a few ulps of values
 // below 2^16) stays far inside the margin, so a tile is skipped only if no
 // sample of it can land in the box.  Uniform across the workgroup.
+//
+// Centre and half extents of the box of target voxels [lo, hi] (inclusive).
+__device__ __forceinline__ void box_centre(const int lo[3], const int hi[3], float c[3], float h[3]) {
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        c[e] = 0.5f * (float)(lo[e] + hi[e]);
+        h[e] = 0.5f * (float)(hi[e] - lo[e]);
+    }
+}
+
+// Whether the image of the box (centre c, half extents h) under the recipe
+// words w can meet the cull box.
+template <typename P>
+__device__ __forceinline__ bool box_reaches(P w, const float c[3], const float h[3], const KArgs &a) {
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float uc = fmaf(w[4 * d + 2], c[2], fmaf(w[4 * d + 1], c[1], fmaf(w[4 * d], c[0], w[4 * d + 3])));
+        const float r = fmaf(fabsf(w[4 * d + 2]), h[2], fmaf(fabsf(w[4 * d + 1]), h[1], fabsf(w[4 * d]) * h[0])) +
+                        kCullMargin;
+        ok = ok && uc + r >= a.cull_lo[d] && uc - r <= a.cull_hi[d];
+    }
+    return ok;
+}
+
 template <int PT>
 __device__ __forceinline__ uint32_t live_mask(const KArgs &a, const Tile &t, uint32_t bx) {
     const int tiles = a.tiles_x * a.tiles_y;
@@ -159,25 +184,13 @@ __device__ __forceinline__ uint32_t live_mask(const KArgs &a, const Tile &t, uin
     const int lo[3] = {tx * kTX, ty * kTY, t.k0};
     const int hi[3] = {min(tx * kTX + kTX - 1, a.tn0 - 1), min(ty * kTY + kTY - 1, a.tn1 - 1), t.k1 - 1};
     float c[3], h[3];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-        c[e] = 0.5f * (float)(lo[e] + hi[e]);
-        h[e] = 0.5f * (float)(hi[e] - lo[e]);
-    }
+    box_centre(lo, hi, c, h);
     const uint32_t last = a.p0 + a.np - 1;
     uint32_t live = 0;
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
         const auto *w = as_const(a.words) + 12 * (size_t)min(t.pbase + (uint32_t)p, last);
-        bool ok = p < t.npg;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const float uc = fmaf(w[4 * d + 2], c[2], fmaf(w[4 * d + 1], c[1], fmaf(w[4 * d], c[0], w[4 * d + 3])));
-            const float r = fmaf(fabsf(w[4 * d + 2]), h[2], fmaf(fabsf(w[4 * d + 1]), h[1], fabsf(w[4 * d]) * h[0])) +
-                            kCullMargin;
-            ok = ok && uc + r >= a.cull_lo[d] && uc - r <= a.cull_hi[d];
-        }
-        live |= ok ? (1u << p) : 0u;
+        live |= (p < t.npg && box_reaches(w, c, h, a)) ? (1u << p) : 0u;
     }
     return live;
 }
@@ -248,10 +261,11 @@ __device__ __forceinline__ uint32_t mad_u24v(uint32_t a, uint32_t b, uint32_t c)
 // bitmap puts the rows of a slice 4 ceil(nx / 32) bytes apart, so the rotated
 // footprint of a wave's samples spans a few cache lines instead of one or two
 // per source row and slice as with a byte per voxel.
-template <int PT, bool AC = false>
-__device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t by) {
+template <int PT, bool AC = false, bool GIVEN = false>
+__device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t by, uint32_t live_in = 0u) {
     const Tile t = tile_of<PT>(a, bx, by);
-    const uint32_t live = live_mask<PT>(a, t, bx);
+    // GIVEN: the cull pre-pass already tested this item (live_in != 0)
+    const uint32_t live = GIVEN ? live_in : live_mask<PT>(a, t, bx);
     if (live == 0u) return;  // nothing of this tile can reach the source region
     float mx[PT], my[PT], mz[PT], ax[PT], ay[PT], az[PT];
     column_terms<PT>(a, t, mx, my, mz, ax, ay, az);
@@ -906,6 +920,89 @@ void k_score_image(const KArgs a) {
     image_body<PT, LAYOUT, TRI, VMODE, ACC>(a, bx, by);
 }
 
+// ---------------------------------------------------------------- culled item lists
+
+// Most (tile, particle group) items of a filter's mask launch cannot reach
+// the source mask's bounding box (a concentrated cloud maps most tiles
+// outside it).  Instead of a grid of one workgroup per item, most of which
+// would only run the cull test and leave, a pre-pass tests every item on its
+// own lane and appends the live ones, with their masks, to eight lists --
+// list x holds the live items of the x-th contiguous eighth of the item
+// sequence, the part the XCD-aware grid gives XCD x -- and a persistent grid
+// takes items from its XCD's list through an atomic counter, then helps the
+// other lists.  Sums are integer additions, so the result does not depend on
+// which workgroup takes which item.
+constexpr uint32_t kListStride = 32;  // counter words 128 bytes apart
+
+__device__ __forceinline__ uint32_t list_begin(uint32_t total, uint32_t x) {
+    const uint32_t q = total / 8u, rem = total % 8u;
+    return x * q + min(x, rem);
+}
+
+template <int PT>
+__global__ __launch_bounds__(256) void k_cull_items(const KArgs a, uint32_t total, uint2 *items, uint32_t *counts) {
+    const uint32_t w = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t groups = (a.np + PT - 1) / PT;
+    uint32_t live = 0u, x = 0u;
+    if (w < total) {
+        const uint32_t bx = w / groups, by = w - bx * groups;
+        const int tiles = a.tiles_x * a.tiles_y;
+        const int zc = (int)bx / tiles, b = (int)bx - zc * tiles;
+        const int ty = b / a.tiles_x, tx = b - ty * a.tiles_x;
+        const int k0 = zc * a.zchunk;
+        const int lo[3] = {tx * kTX, ty * kTY, k0};
+        const int hi[3] = {min(tx * kTX + kTX - 1, a.tn0 - 1), min(ty * kTY + kTY - 1, a.tn1 - 1),
+                           min(k0 + a.zchunk, a.tn2) - 1};
+        float c[3], h[3];
+        box_centre(lo, hi, c, h);
+        const uint32_t pbase = a.p0 + by * PT, npg = min((uint32_t)PT, a.p0 + a.np - pbase);
+        for (uint32_t p = 0; p < npg; ++p)
+            if (box_reaches(a.words + 12 * (size_t)(pbase + p), c, h, a)) live |= 1u << p;
+        while (x < 7u && w >= list_begin(total, x + 1u)) ++x;
+    }
+    // one atomic per wave when all its lanes fall in one list (the usual case)
+    const uint32_t lane = threadIdx.x % 64u;
+    const uint32_t x0 = __shfl(x, 0);
+    const bool one_list = __all(x == x0);
+    const uint64_t m = __ballot(live != 0u);
+    if (one_list) {
+        if (m == 0ull) return;
+        uint32_t base = 0u;
+        if (lane == 0u) base = atomicAdd(counts + x0 * kListStride, (uint32_t)__popcll(m));
+        base = __shfl(base, 0);
+        if (live) {
+            const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            items[list_begin(total, x0) + base + rank] = make_uint2(w, live);
+        }
+    } else if (live) {
+        const uint32_t pos = atomicAdd(counts + x * kListStride, 1u);
+        items[list_begin(total, x) + pos] = make_uint2(w, live);
+    }
+}
+
+template <int PT>
+__global__ __launch_bounds__(kThreads) void k_score_mask_items(const KArgs a, const uint2 *items,
+                                                               const uint32_t *counts, uint32_t *take,
+                                                               uint32_t total) {
+    __shared__ uint32_t next_item;
+    const uint32_t groups = (a.np + PT - 1) / PT;
+    for (uint32_t s = 0; s < 8; ++s) {
+        const uint32_t x = (blockIdx.x + s) % 8u;
+        const uint32_t begin = list_begin(total, x), n_items = counts[x * kListStride];
+        for (;;) {
+            if (threadIdx.x == 0) next_item = atomicAdd(take + x * kListStride, 1u);
+            __syncthreads();
+            const uint32_t r = next_item;
+            if (r >= n_items) break;
+            const uint2 it = items[begin + r];
+            const uint32_t bx = it.x / groups, by = it.x - bx * groups;
+            mask_body<PT, true, true>(a, bx, by, it.y);
+            __syncthreads();  // next_item is read by all before thread 0 takes the next
+        }
+        __syncthreads();  // the same before the next list's first take
+    }
+}
+
 // ---------------------------------------------------------------- batches
 
 // Persistent warp-and-score over the work items of many pairs.  Item g of
@@ -1174,6 +1271,69 @@ void score_grid(const ScoreLaunch &L, dim3 *grid, dim3 *block) {
     *block = dim3(kThreads, 1, 1);
 }
 
+namespace {
+
+template <int PT>
+__global__ __launch_bounds__(kThreads) void k_probe_mask_items(const KArgs a, const uint2 *items,
+                                                               const uint32_t *counts, uint32_t *take,
+                                                               uint32_t total, uint32_t key, uint32_t *out);
+
+// Resident workgroups of a persistent kernel on the current device.
+int persistent_blocks(const void *kernel) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 4;
+    return cus * per_cu;
+}
+
+template <int PT>
+hipError_t launch_mask_items_pt(const KArgs &a, uint32_t total, const ScoreLaunch &L, bool probe, uint32_t key,
+                                uint32_t *out, hipStream_t s) {
+    static_assert(kItemCounterWords == 16 * kListStride, "counts and takes, eight each");
+    uint32_t *counts = L.item_counters, *take = L.item_counters + 8 * kListStride;
+    hipError_t e = launch_fill_u64((unsigned long long *)L.item_counters, kItemCounterWords / 2, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cull_items<PT>, dim3((total + 255u) / 256u), dim3(256), 0, s, a, total, (uint2 *)L.items,
+                       counts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (probe) {
+        static int blocks = 0;
+        if (!blocks) blocks = persistent_blocks(reinterpret_cast<const void *>(k_probe_mask_items<PT>));
+        hipLaunchKernelGGL(k_probe_mask_items<PT>, dim3(blocks), dim3(kThreads), 0, s, a, (const uint2 *)L.items,
+                           (const uint32_t *)counts, take, total, key, out);
+    } else {
+        static int blocks = 0;
+        if (!blocks) blocks = persistent_blocks(reinterpret_cast<const void *>(k_score_mask_items<PT>));
+        hipLaunchKernelGGL(k_score_mask_items<PT>, dim3(blocks), dim3(kThreads), 0, s, a, (const uint2 *)L.items,
+                           (const uint32_t *)counts, take, total);
+    }
+    return hipGetLastError();
+}
+
+// The filter's mask launches through the culled item lists, when the
+// context provides lists large enough for this launch.
+bool uses_item_lists(const ScoreLaunch &L, uint64_t total) {
+    return L.mode == kModeMask && L.cull_box && L.src_bits && L.items && L.item_counters && total <= L.item_cap;
+}
+
+hipError_t launch_mask_items(const ScoreLaunch &L, int pt, const KArgs &a, uint32_t total, bool probe, uint32_t key,
+                             uint32_t *out, hipStream_t s) {
+    if (pt == 4) return launch_mask_items_pt<4>(a, total, L, probe, key, out, s);
+    if (pt == 16) return launch_mask_items_pt<16>(a, total, L, probe, key, out, s);
+    return launch_mask_items_pt<8>(a, total, L, probe, key, out, s);
+}
+
+}  // namespace
+
+uint64_t score_items_for(const ScoreLaunch &L) {
+    dim3 grid, block;
+    score_grid(L, &grid, &block);
+    return (uint64_t)grid.x * grid.y;
+}
+
 hipError_t launch_score(const ScoreLaunch &L, hipStream_t s) {
     if (L.np == 0) return hipSuccess;
     int chunks;
@@ -1181,6 +1341,7 @@ hipError_t launch_score(const ScoreLaunch &L, hipStream_t s) {
     const KArgs a = make_args(L, pt, &chunks);
     dim3 grid, block;
     score_grid(L, &grid, &block);
+    if (uses_item_lists(L, grid.x)) return launch_mask_items(L, pt, a, grid.x, false, 0u, nullptr, s);
     ScoreKernel k = pt == 4 ? pick<4>(L) : (pt == 16 ? pick<16>(L) : pick<8>(L));
     hipLaunchKernelGGL(k, grid, block, 0, s, a);
     return hipGetLastError();
@@ -1197,10 +1358,10 @@ hipError_t launch_score(const ScoreLaunch &L, hipStream_t s) {
 // key the host never passes, which keeps every load live.
 namespace {
 
-template <int PT, bool AC>
-__device__ __forceinline__ uint32_t probe_mask_body(const KArgs &a, uint32_t bx, uint32_t by) {
+template <int PT, bool AC, bool GIVEN = false>
+__device__ __forceinline__ uint32_t probe_mask_body(const KArgs &a, uint32_t bx, uint32_t by, uint32_t live_in = 0u) {
     const Tile t = tile_of<PT>(a, bx, by);
-    const uint32_t live = live_mask<PT>(a, t, bx);
+    const uint32_t live = GIVEN ? live_in : live_mask<PT>(a, t, bx);
     uint32_t chk = 0u;
     if (live == 0u || !t.ok) return chk;
     float mx[PT], my[PT], mz[PT], ax[PT], ay[PT], az[PT];
@@ -1293,6 +1454,31 @@ __global__ __launch_bounds__(kThreads) void k_gather_probe(const KArgs a, uint32
 }
 
 template <int PT>
+__global__ __launch_bounds__(kThreads) void k_probe_mask_items(const KArgs a, const uint2 *items,
+                                                               const uint32_t *counts, uint32_t *take,
+                                                               uint32_t total, uint32_t key, uint32_t *out) {
+    __shared__ uint32_t next_item;
+    const uint32_t groups = (a.np + PT - 1) / PT;
+    uint32_t chk = 0u;
+    for (uint32_t s = 0; s < 8; ++s) {
+        const uint32_t x = (blockIdx.x + s) % 8u;
+        const uint32_t begin = list_begin(total, x), n_items = counts[x * kListStride];
+        for (;;) {
+            if (threadIdx.x == 0) next_item = atomicAdd(take + x * kListStride, 1u);
+            __syncthreads();
+            const uint32_t r = next_item;
+            if (r >= n_items) break;
+            const uint2 it = items[begin + r];
+            const uint32_t bx = it.x / groups, by = it.x - bx * groups;
+            chk ^= probe_mask_body<PT, true, true>(a, bx, by, it.y);
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+    if (chk == key) out[0] = chk;
+}
+
+template <int PT>
 ScoreKernel probe_kernel(const ScoreLaunch &L) {
     typedef void (*PK)(const KArgs, uint32_t, uint32_t *);
     PK k = nullptr;
@@ -1325,6 +1511,8 @@ hipError_t launch_gather_probe(const ScoreLaunch &L, uint32_t key, uint32_t *out
     const KArgs a = make_args(L, pt, &chunks);
     dim3 grid, block;
     score_grid(L, &grid, &block);
+    // the same schedule as the production launch (culled item lists or grid)
+    if (uses_item_lists(L, grid.x)) return launch_mask_items(L, pt, a, grid.x, true, key, out, s);
     ScoreKernel k = pt == 4 ? probe_kernel<4>(L) : (pt == 16 ? probe_kernel<16>(L) : probe_kernel<8>(L));
     typedef void (*PK)(const KArgs, uint32_t, uint32_t *);
     hipLaunchKernelGGL(reinterpret_cast<PK>(k), grid, block, 0, s, a, key, out);
