@@ -1340,6 +1340,16 @@ smc_status plan_class(smc_batch *b, smc_batch::Class &C, int mode, int vmode) {
         (st = b->alloc(&C.kmax, n)) != SMC_OK || (st = b->alloc(&C.lists, flat.size())) != SMC_OK ||
         (st = b->alloc(&C.plan.counters, 8ull * std::max(1u, b->kmax_all))) != SMC_OK)
         return st;
+    if (mode == kModeMask) {
+        // live item lists of the cull pre-pass (one list buffer, counts per iteration)
+        uint2 *live = nullptr;
+        uint32_t *lc = nullptr;
+        if ((st = b->alloc(&live, std::max<size_t>(1, flat.size()))) != SMC_OK ||
+            (st = b->alloc(&lc, (size_t)(kItemCounterWords / 2) * std::max(1u, b->kmax_all))) != SMC_OK)
+            return st;
+        C.plan.live = live;
+        C.plan.live_counts = lc;
+    }
     HIP_TRY(hipMemcpy(C.args, args.data(), args.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(C.offs, offs.data(), 4 * (n + 1), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(C.kmax, kmax.data(), 4 * n, hipMemcpyHostToDevice));
@@ -1424,6 +1434,9 @@ smc_status record_run(smc_batch *b) {
         if (b->cls[q].plan.n_pairs)
             HIP_TRY(launch_fill_u64((unsigned long long *)b->cls[q].plan.counters, 4ull * std::max(1u, b->kmax_all),
                                     b->stream));
+    if (b->cls[0].plan.n_pairs && b->cls[0].plan.live_counts)
+        HIP_TRY(launch_fill_u64((unsigned long long *)b->cls[0].plan.live_counts,
+                                (uint64_t)(kItemCounterWords / 4) * std::max(1u, b->kmax_all), b->stream));
     for (uint32_t k = 1; k <= b->kmax_all; ++k) {
         for (int q = 0; q < 4; ++q) {
             const smc_batch::Class &C = b->cls[q];

@@ -99,6 +99,11 @@ struct BatchPlan {
     // item queues: 8 counters (one per XCD list) per iteration, zero before
     // the run; iteration k uses counters[8 (k - 1) .. 8 k)
     uint32_t *counters;
+    // masks: per iteration a cull pre-pass appends the live items (item id,
+    // particle mask) of list x to live[list_off[x] ..), counted in
+    // live_counts[kItemCounterWords / 2 (k - 1) + 32 x] (zero before the run)
+    void *live = nullptr;
+    uint32_t *live_counts = nullptr;
 };
 size_t score_args_bytes();
 uint32_t score_items(const ScoreLaunch &L);

@@ -1071,6 +1071,86 @@ void k_batch_score(const BatchArgs b) {
     }
 }
 
+// Mask classes: the live items of an iteration.  One thread per entry of the
+// class's XCD lists tests its (tile, particle group) item against its pair's
+// source mask box and appends live items, with their particle masks, to the
+// same list's part of `live` (one atomic per wave where all its lanes are in
+// one list); pairs past their last iteration add nothing.
+template <int PT>
+__global__ __launch_bounds__(256) void k_batch_cull(const BatchArgs b, uint2 *live, uint32_t *counts) {
+    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t total = b.list_off[8];
+    uint32_t lm = 0u, x = 0u, g = 0u;
+    if (e < total) {
+        while (x < 7u && e >= b.list_off[x + 1]) ++x;
+        g = b.lists[e];
+        const uint32_t d = pair_of(b.offs, b.n_pairs, g);
+        if (b.kmax[d] >= b.k) {
+            const KArgs &a = b.pairs[d];
+            const uint32_t local = g - b.offs[d];
+            const uint32_t groups = (a.np + PT - 1) / PT;
+            const uint32_t bx = local / groups, by = local - bx * groups;
+            const int tiles = a.tiles_x * a.tiles_y;
+            const int zc = (int)bx / tiles, tb = (int)bx - zc * tiles;
+            const int ty = tb / a.tiles_x, tx = tb - ty * a.tiles_x;
+            const int k0 = zc * a.zchunk;
+            const int lo[3] = {tx * kTX, ty * kTY, k0};
+            const int hi[3] = {min(tx * kTX + kTX - 1, a.tn0 - 1), min(ty * kTY + kTY - 1, a.tn1 - 1),
+                               min(k0 + a.zchunk, a.tn2) - 1};
+            float c[3], h[3];
+            box_centre(lo, hi, c, h);
+            const uint32_t pbase = a.p0 + by * PT, npg = min((uint32_t)PT, a.p0 + a.np - pbase);
+            for (uint32_t p = 0; p < npg; ++p)
+                if (box_reaches(a.words + 12 * (size_t)(pbase + p), c, h, a)) lm |= 1u << p;
+        }
+    }
+    const uint32_t lane = threadIdx.x % 64u;
+    const uint32_t x0 = __shfl(x, 0);
+    const bool one_list = __all(x == x0);
+    const uint64_t m = __ballot(lm != 0u);
+    if (one_list) {
+        if (m == 0ull) return;
+        uint32_t base = 0u;
+        if (lane == 0u) base = atomicAdd(counts + x0 * kListStride, (uint32_t)__popcll(m));
+        base = __shfl(base, 0);
+        if (lm) {
+            const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            live[b.list_off[x0] + base + rank] = make_uint2(g, lm);
+        }
+    } else if (lm) {
+        const uint32_t pos = atomicAdd(counts + x * kListStride, 1u);
+        live[b.list_off[x] + pos] = make_uint2(g, lm);
+    }
+}
+
+// The mask class's persistent warp-and-score over the live items of one
+// iteration: list x first (its XCD's), then the others, as k_batch_score.
+template <int PT>
+__global__ __launch_bounds__(kThreads) void k_batch_mask_items(const BatchArgs b, const uint2 *live,
+                                                               const uint32_t *counts) {
+    const auto *pairs = as_const(b.pairs);
+    __shared__ uint32_t next_item;
+    for (uint32_t s = 0; s < 8; ++s) {
+        const uint32_t x = (blockIdx.x + s) % 8;
+        const uint32_t begin = b.list_off[x], n_items = counts[x * kListStride];
+        for (;;) {
+            if (threadIdx.x == 0) next_item = atomicAdd(b.counters + x, 1u);
+            __syncthreads();
+            const uint32_t r = next_item;
+            if (r >= n_items) break;
+            const uint2 it = live[begin + r];
+            const uint32_t d = pair_of(b.offs, b.n_pairs, it.x);
+            const KArgs a = pairs[d];
+            const uint32_t local = it.x - b.offs[d];
+            const uint32_t ng = (a.np + PT - 1) / PT;
+            const uint32_t bx = local / ng, by = local - bx * ng;
+            mask_body<PT, true, true>(a, bx, by, it.y);
+            __syncthreads();  // next_item is read by all before thread 0 takes the next
+        }
+        __syncthreads();  // the same before the next list's first take
+    }
+}
+
 KArgs make_args(const ScoreLaunch &L, int pt, int *nz_chunks) {
     KArgs a;
     a.src = L.src;
@@ -1237,6 +1317,28 @@ hipError_t launch_batch_score(const BatchPlan &P, uint32_t k, hipStream_t s) {
     b.n_pairs = P.n_pairs;
     b.k = k;
     b.counters = P.counters + 8ull * (k - 1);
+    if (P.mode == kModeMask && P.live && P.live_counts) {
+        const int pt = score_pt_supported(P.pt) ? P.pt : 8;
+        uint32_t *counts = P.live_counts + (uint64_t)(kItemCounterWords / 2) * (k - 1);
+        const uint32_t total = P.list_off[8];
+        const dim3 cg((total + 255u) / 256u);
+        if (total == 0) return hipSuccess;
+        if (pt == 4) hipLaunchKernelGGL(k_batch_cull<4>, cg, dim3(256), 0, s, b, (uint2 *)P.live, counts);
+        else if (pt == 16) hipLaunchKernelGGL(k_batch_cull<16>, cg, dim3(256), 0, s, b, (uint2 *)P.live, counts);
+        else hipLaunchKernelGGL(k_batch_cull<8>, cg, dim3(256), 0, s, b, (uint2 *)P.live, counts);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (pt == 4)
+            hipLaunchKernelGGL(k_batch_mask_items<4>, dim3(P.grid), dim3(kThreads), 0, s, b, (const uint2 *)P.live,
+                               (const uint32_t *)counts);
+        else if (pt == 16)
+            hipLaunchKernelGGL(k_batch_mask_items<16>, dim3(P.grid), dim3(kThreads), 0, s, b, (const uint2 *)P.live,
+                               (const uint32_t *)counts);
+        else
+            hipLaunchKernelGGL(k_batch_mask_items<8>, dim3(P.grid), dim3(kThreads), 0, s, b, (const uint2 *)P.live,
+                               (const uint32_t *)counts);
+        return hipGetLastError();
+    }
     typedef void (*BK)(const BatchArgs);
     BK kern = reinterpret_cast<BK>(const_cast<void *>(batch_kernel(P)));
     hipLaunchKernelGGL(kern, dim3(P.grid), dim3(kThreads), 0, s, b);
@@ -1245,6 +1347,11 @@ hipError_t launch_batch_score(const BatchPlan &P, uint32_t k, hipStream_t s) {
 
 const void *batch_kernel(const BatchPlan &P) {
     const int pt = score_pt_supported(P.pt) ? P.pt : 8;
+    if (P.mode == kModeMask && P.live) {
+        if (pt == 4) return reinterpret_cast<const void *>(k_batch_mask_items<4>);
+        if (pt == 16) return reinterpret_cast<const void *>(k_batch_mask_items<16>);
+        return reinterpret_cast<const void *>(k_batch_mask_items<8>);
+    }
     if (pt == 4) return reinterpret_cast<const void *>(pick_batch_pt<4>(P));
     if (pt == 16) return reinterpret_cast<const void *>(pick_batch_pt<16>(P));
     return reinterpret_cast<const void *>(pick_batch_pt<8>(P));
