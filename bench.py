@@ -506,7 +506,7 @@ def main():
                     help="layout,particles_per_group,tile_depth of the speckle160 warp-and-score launch")
     ap.add_argument("--lv-frames", type=int, default=LV_FRAMES,
                     help="frames of the lv224 sequence generated and warped (the workload has 20)")
-    ap.add_argument("--only", choices=["lv224", "speckle160", "batch64"], default=None,
+    ap.add_argument("--only", choices=["lv224", "speckle160", "batch64", "ttd"], default=None,
                     help="run one workload alone and print its line (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 256 MiB (three times), to scale HBM byte counters")
@@ -521,7 +521,8 @@ def main():
     if args.only is not None:
         args.no_speckle = args.only != "speckle160"
         args.no_batch = args.only != "batch64"
-        args.no_time_to_dice = args.no_cpu_baseline = True
+        args.no_time_to_dice = args.only != "ttd"
+        args.no_cpu_baseline = True
 
     inp = make_inputs(args)  # before anything initialises the GPU
 
@@ -538,6 +539,9 @@ def main():
         return
     if args.only == "batch64":
         print(json.dumps(dict(batch64(inp, args), n_gpus=1)), flush=True)
+        return
+    if args.only == "ttd":
+        print(json.dumps(dict(time_to_dice(inp, args) or {}, n_gpus=1)), flush=True)
         return
     h = lv224(inp, args)
     line = {

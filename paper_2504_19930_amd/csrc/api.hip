@@ -1651,8 +1651,10 @@ smc_status smc_cnn_create(smc_cnn **out, uint32_t max_batch, void *hip_stream) {
         (st = n->alloc(&n->input, 2 * side3 * max_batch)) != SMC_OK ||
         (st = n->alloc(&n->out, 12ull * max_batch)) != SMC_OK ||
         (st = n->alloc(&n->target, 12ull * max_batch)) != SMC_OK || (st = n->alloc(&n->loss, 4)) != SMC_OK ||
-        (st = n->alloc(&c.dout, 12ull * max_batch)) != SMC_OK)
+        (st = n->alloc(&c.dout, 12ull * max_batch)) != SMC_OK ||
+        (st = n->alloc(&c.partial, (size_t)cnn_partial_floats((int)max_batch))) != SMC_OK)
         return bail(st);
+    c.partial_cap = cnn_partial_floats((int)max_batch);
     for (int L = 0; L < 4; ++L) {
         const size_t d = (size_t)(kCnnSide >> (L + 1));
         const size_t elems = (size_t)max_batch * kCnnChannels[L + 1] * d * d * d;

@@ -3,9 +3,17 @@
 // ReLU), a linear head to 6 means and 6 log-variances, the Gaussian NLL of
 // the filter's final weighted cloud, its backward pass and Adam.
 //
-// Convolutions are implicit GEMMs on the matrix cores: one wave owns a 16x16
-// output tile and issues v_mfma_f32_16x16x16_bf16 over K in steps of 16, its
-// operands gathered straight from the activations (no im2col buffer).
+// Convolutions are implicit GEMMs on the matrix cores, their operands
+// gathered straight from the activations (no im2col buffer).  The forward
+// pass (k_conv_fwd) gives each workgroup one 16x16 output tile and a range of
+// K: its four waves take alternate 32-wide steps of v_mfma_f32_16x16x32_bf16
+// (gfx950's BF16 matrix instruction, eight K values per lane), with the
+// im2col offsets of the range precomputed in LDS, and their accumulators are
+// added in LDS.  The deep layers have few output tiles, so K is also split
+// across workgroups, whose partial tiles a second kernel adds in a fixed
+// order with the bias and ReLU (no floating-point atomics: a forward pass is
+// reproducible bit for bit).  The backward operators use one wave per 16x16
+// tile and v_mfma_f32_16x16x16_bf16.
 //   forward  C[m = output voxel][n = c_out]  = sum_k X(m, k = (c_in, kz, ky, kx)) W(k, n)
 //   dgrad    C[m = input voxel][n = c_in]    = sum_k dY(m, k = (c_out, kz, ky, kx)) W(k, n)
 //   wgrad    C[m = c_out][n = (c_in, kz, ky, kx)] = sum_k dY(k = output voxel, m) X(k, n)   (split-K)
@@ -164,6 +172,126 @@ hipError_t run_gemm(const Op &op, int splits, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---- forward convolution --------------------------------------------------------
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kFwdMaxK = 64 * 27;  // largest K = c_in * 27 of the network
+
+// One workgroup: output rows m0 .. m0 + 15 (output voxels, with batch),
+// channels n0 .. n0 + 15, K steps [s0, s1) of 32.  Wave w takes steps
+// s0 + w, s0 + w + 4, ...; lane l gathers A[m0 + l % 16][k0 + 8 (l / 16) + j]
+// and B[k0 + 8 (l / 16) + j][n0 + l % 16], j = 0..7, and holds
+// C[m0 + 4 (l / 16) + i][n0 + l % 16], i = 0..3.  splits == 1: bias, ReLU and
+// BF16 rounding here; otherwise the FP32 partial tile goes to
+// partial[split][m][n] for k_conv_fwd_finish.
+template <bool HALF_IN>
+__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *X, const uint16_t *W, const float *bias,
+                                                  uint16_t *Y, float *partial, ConvShape sh, int M, int N, int K,
+                                                  int steps_per_split) {
+    __shared__ int32_t koff[kFwdMaxK];  // (c, kz, ky, kx) -> input offset, low 3 bits: kz/ky/kx == 0
+    __shared__ v4f red[3][64];
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int m0 = blockIdx.x * 16, n0 = blockIdx.y * 16, split = blockIdx.z;
+    const int di = sh.di, dout = di / 2, vin = di * di * di, vox = dout * dout * dout;
+    const int k_begin = split * steps_per_split * 32, k_end = min(K, k_begin + steps_per_split * 32);
+    for (int k = k_begin + (int)threadIdx.x; k < k_end; k += 256) {
+        const int c = k / 27, t = k - 27 * c, kz = t / 9, ky = (t / 3) % 3, kx = t % 3;
+        const int off = c * vin + (kz - 1) * di * di + (ky - 1) * di + (kx - 1);
+        koff[k - k_begin] = off * 8 + (kz == 0 ? 4 : 0) + (ky == 0 ? 2 : 0) + (kx == 0 ? 1 : 0);
+    }
+    __syncthreads();
+    // this lane's output voxel (row of A)
+    const int r = lane % 16, g = lane / 16;
+    const int m = m0 + r;
+    const bool mrow = m < M;
+    const int b = mrow ? m / vox : 0, rr = mrow ? m - b * vox : 0;
+    const int oz = rr / (dout * dout), oy = (rr / dout) % dout, ox = rr % dout;
+    const int base = b * sh.ci * vin + 2 * oz * di * di + 2 * oy * di + 2 * ox;
+    // kz == 0 reads z = 2 oz - 1, outside only on the first output slice (likewise y, x)
+    const int edge = (oz == 0 ? 4 : 0) | (oy == 0 ? 2 : 0) | (ox == 0 ? 1 : 0);
+    const int n = n0 + r;
+    const bool ncol = n < N;
+    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    const int nsteps = (k_end - k_begin + 31) / 32;
+    for (int st = wave; st < nsteps; st += 4) {
+        const int kl = st * 32 + 8 * g;  // local K index of this lane's first value
+        bf16x8 av, bv;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = k_begin + kl + j;
+            uint16_t a = 0, w = 0;
+            if (k < k_end) {
+                const int e = koff[kl + j];
+                if (mrow && (e & edge) == 0) {
+                    const uint16_t v = X[base + (e >> 3)];
+                    a = HALF_IN ? to_bf16(__half2float(__ushort_as_half(v))) : v;
+                }
+                if (ncol) w = W[(size_t)n * K + k];
+            }
+            av[j] = __builtin_bit_cast(__bf16, a);
+            bv[j] = __builtin_bit_cast(__bf16, w);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    }
+    if (wave > 0) red[wave - 1][lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    acc += red[0][lane];
+    acc += red[1][lane];
+    acc += red[2][lane];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int mo = m0 + 4 * g + i;
+        if (mo >= M || !ncol) continue;
+        if (gridDim.z == 1) {
+            const int bo = mo / vox, ro = mo - bo * vox;
+            Y[((size_t)bo * N + n) * vox + ro] = to_bf16(fmaxf(acc[i] + bias[n], 0.0f));
+        } else {
+            partial[((size_t)split * M + mo) * N + n] = acc[i];
+        }
+    }
+}
+
+// Sum of the split-K partial tiles in split order, bias, ReLU, BF16.
+__global__ __launch_bounds__(256) void k_conv_fwd_finish(const float *partial, const float *bias, uint16_t *Y,
+                                                         int M, int N, int vox, int splits) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= M * N) return;
+    const int mo = q / N, n = q - mo * N;
+    float v = 0.0f;
+    for (int sp = 0; sp < splits; ++sp) v += partial[((size_t)sp * M + mo) * N + n];
+    const int bo = mo / vox, ro = mo - bo * vox;
+    Y[((size_t)bo * N + n) * vox + ro] = to_bf16(fmaxf(v + bias[n], 0.0f));
+}
+
+// K splits of a forward layer: enough workgroups to spread over the chip
+// (about 512), at least one 32-step per wave, within the partial buffer.
+int fwd_splits(int M, int N, int K, int64_t cap) {
+    const int tiles = ((M + 15) / 16) * ((N + 15) / 16);
+    const int steps = (K + 31) / 32;
+    int sp = std::max(1, std::min((512 + tiles - 1) / tiles, steps / 4));
+    while (sp > 1 && (int64_t)sp * M * N > cap) --sp;
+    return sp;
+}
+
+template <bool HALF_IN>
+hipError_t conv_fwd(const uint16_t *X, const uint16_t *W, const float *bias, uint16_t *Y, float *partial,
+                    int64_t cap, const ConvShape &sh, hipStream_t s) {
+    const int dout = sh.di / 2, vox = dout * dout * dout;
+    const int M = sh.B * vox, N = sh.co, K = sh.ci * 27;
+    const int steps = (K + 31) / 32;
+    const int sp = fwd_splits(M, N, K, cap);
+    const int sps = (steps + sp - 1) / sp;
+    const int nsplit = (steps + sps - 1) / sps;
+    dim3 grid((M + 15) / 16, (N + 15) / 16, nsplit);
+    hipLaunchKernelGGL(k_conv_fwd<HALF_IN>, grid, dim3(256), 0, s, X, W, bias, Y, partial, sh, M, N, K, sps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nsplit == 1) return e;
+    hipLaunchKernelGGL(k_conv_fwd_finish, dim3((M * N + 255) / 256), dim3(256), 0, s, (const float *)partial, bias, Y,
+                       M, N, vox, nsplit);
+    return hipGetLastError();
+}
+
 // ---- small kernels -----------------------------------------------------------
 
 // Trilinear resampling to side^3 at half-pixel centres, FP16 output.
@@ -317,6 +445,18 @@ int64_t cnn_param_offset(int part) {
     return o;
 }
 
+int64_t cnn_partial_floats(int max_batch) {
+    int64_t most = 1;
+    for (int L = 0; L < 4; ++L) {
+        const int d = (kCnnSide >> L) / 2;
+        for (int B = 1; B <= max_batch; ++B) {
+            const int M = B * d * d * d, N = kCnnChannels[L + 1], K = kCnnChannels[L] * 27;
+            most = std::max(most, (int64_t)fwd_splits(M, N, K, INT64_MAX) * M * N);
+        }
+    }
+    return std::min<int64_t>(most, (int64_t)1 << 22);
+}
+
 hipError_t cnn_downsample(const uint8_t *vol, const int32_t n[3], float scale, uint16_t *out, hipStream_t s) {
     const int tot = kCnnSide * kCnnSide * kCnnSide;
     hipLaunchKernelGGL(k_downsample, dim3((tot + 255) / 256), dim3(256), 0, s, vol, n[0], n[1], n[2], scale, kCnnSide,
@@ -331,10 +471,10 @@ hipError_t cnn_forward(const CnnBuffers &c, const uint16_t *input, int B, float 
         const int dout = sh.di / 2;
         const uint16_t *W = c.wbf16 + cnn_param_offset(2 * L);
         const float *bias = c.params + cnn_param_offset(2 * L + 1);
-        const int M = B * dout * dout * dout, N = sh.co, K = sh.ci * 27;
+        (void)dout;
         hipError_t e;
-        if (L == 0) e = run_gemm(FwdOp<true>{x, W, bias, c.act[0], sh, M, N, K}, 1, s);
-        else e = run_gemm(FwdOp<false>{x, W, bias, c.act[L], sh, M, N, K}, 1, s);
+        if (L == 0) e = conv_fwd<true>(x, W, bias, c.act[0], c.partial, c.partial_cap, sh, s);
+        else e = conv_fwd<false>(x, W, bias, c.act[L], c.partial, c.partial_cap, sh, s);
         if (e != hipSuccess) return e;
         x = c.act[L];
     }

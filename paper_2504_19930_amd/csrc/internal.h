@@ -195,7 +195,11 @@ struct CnnBuffers {
     uint16_t *act[4];    // layer outputs after ReLU, bfloat16
     float *dact[4];      // gradients w.r.t. layer pre-activations
     float *dout;         // B x 12
+    float *partial;      // split-K partial tiles of the forward convolutions
+    int64_t partial_cap; // floats in partial
 };
+// Floats of the forward split-K buffer a network of max_batch pairs needs.
+int64_t cnn_partial_floats(int max_batch);
 int64_t cnn_param_offset(int part);
 hipError_t cnn_downsample(const uint8_t *vol, const int32_t n[3], float scale, uint16_t *out, hipStream_t s);
 hipError_t cnn_forward(const CnnBuffers &c, const uint16_t *input, int B, float *out, hipStream_t s);
