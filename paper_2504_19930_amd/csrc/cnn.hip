@@ -13,7 +13,7 @@
 // across workgroups, whose partial tiles a second kernel adds in a fixed
 // order with the bias and ReLU (no floating-point atomics: a forward pass is
 // reproducible bit for bit).  The backward operators use one wave per 16x16
-// tile and v_mfma_f32_16x16x16_bf16.
+// tile and the same instruction.
 //   forward  C[m = output voxel][n = c_out]  = sum_k X(m, k = (c_in, kz, ky, kx)) W(k, n)
 //   dgrad    C[m = input voxel][n = c_in]    = sum_k dY(m, k = (c_out, kz, ky, kx)) W(k, n)
 //   wgrad    C[m = c_out][n = (c_in, kz, ky, kx)] = sum_k dY(k = output voxel, m) X(k, n)   (split-K)
@@ -26,7 +26,6 @@
 namespace smc {
 namespace {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
@@ -52,30 +51,6 @@ __device__ __forceinline__ uint16_t act_bf16(const uint16_t *X, const ConvShape 
     if (HALF_IN) return to_bf16(__half2float(__ushort_as_half(v)));
     return v;
 }
-
-template <bool HALF_IN>
-struct FwdOp {
-    const uint16_t *X, *W;  // W: [co][ci*27] bf16
-    const float *bias;
-    uint16_t *Y;            // [B][co][do][do][do] bf16
-    ConvShape s;
-    int M, N, K;
-    __device__ uint16_t a(int m, int k) const {
-        const int dout = s.di / 2, vox = dout * dout * dout;
-        const int b = m / vox, r = m - b * vox;
-        const int oz = r / (dout * dout), oy = (r / dout) % dout, ox = r % dout;
-        const int c = k / 27, t = k - 27 * c;
-        const int kz = t / 9, ky = (t / 3) % 3, kx = t % 3;
-        return act_bf16<HALF_IN>(X, s, b, c, 2 * oz + kz - 1, 2 * oy + ky - 1, 2 * ox + kx - 1);
-    }
-    __device__ uint16_t b(int k, int n) const { return W[(size_t)n * K + k]; }
-    __device__ void store(int m, int n, float acc) const {
-        const int dout = s.di / 2, vox = dout * dout * dout;
-        const int b = m / vox, r = m - b * vox;
-        const float v = fmaxf(acc + bias[n], 0.0f);
-        Y[((size_t)b * s.co + n) * vox + r] = to_bf16(v);
-    }
-};
 
 // dL/dX of a convolution (X = relu output of the previous layer, so the
 // stored gradient is masked by X > 0: the gradient of the previous
@@ -134,8 +109,11 @@ struct WgradOp {
 };
 
 // One wave per 16x16 tile of C; four waves per workgroup along M; split-K on
-// grid.z.  Lane l holds A[row l % 16][k0 + 4 (l / 16) + i], B[k0 + 4 (l / 16) + i]
-// [col l % 16] and, after the MFMAs, C[4 (l / 16) + i][col l % 16], i = 0..3.
+// grid.z.  Lane l holds A[row l % 16][k0 + 8 (l / 16) + i], B[k0 + 8 (l / 16) + i]
+// [col l % 16], i = 0..7, for v_mfma_f32_16x16x32_bf16 and, after the MFMAs,
+// C[4 (l / 16) + i][col l % 16], i = 0..3.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
 template <class Op>
 __global__ __launch_bounds__(256) void k_mfma_gemm(const Op op, int k_per_split) {
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -145,16 +123,16 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(const Op op, int k_per_split)
     const int kb = blockIdx.z * k_per_split, ke = min(op.K, kb + k_per_split);
     v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
     const bool mrow = m0 + r < op.M, ncol = n0 + r < op.N;
-    for (int k0 = kb; k0 < ke; k0 += 16) {
-        v4s av, bv;
+    for (int k0 = kb; k0 < ke; k0 += 32) {
+        bf16x8 av, bv;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int k = k0 + 4 * g + i;
+        for (int i = 0; i < 8; ++i) {
+            const int k = k0 + 8 * g + i;
             const bool kin = k < ke;
-            av[i] = (short)(kin && mrow ? op.a(m0 + r, k) : 0);
-            bv[i] = (short)(kin && ncol ? op.b(k, n0 + r) : 0);
+            av[i] = __builtin_bit_cast(__bf16, (uint16_t)(kin && mrow ? op.a(m0 + r, k) : 0));
+            bv[i] = __builtin_bit_cast(__bf16, (uint16_t)(kin && ncol ? op.b(k, n0 + r) : 0));
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -165,7 +143,7 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(const Op op, int k_per_split)
 
 template <class Op>
 hipError_t run_gemm(const Op &op, int splits, hipStream_t s) {
-    const int kps = ((op.K + splits - 1) / splits + 15) / 16 * 16;
+    const int kps = ((op.K + splits - 1) / splits + 31) / 32 * 32;
     const int nsplit = (op.K + kps - 1) / kps;
     dim3 grid((op.M + 63) / 64, (op.N + 15) / 16, nsplit);
     hipLaunchKernelGGL(k_mfma_gemm<Op>, grid, dim3(256), 0, s, op, kps);
@@ -174,7 +152,6 @@ hipError_t run_gemm(const Op &op, int splits, hipStream_t s) {
 
 // ---- forward convolution --------------------------------------------------------
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kFwdMaxK = 64 * 27;  // largest K = c_in * 27 of the network
 
 // One workgroup: output rows m0 .. m0 + 15 (output voxels, with batch),
