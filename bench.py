@@ -19,8 +19,8 @@ second, V the nominal target grid).  The JSON line also carries
 * cpu_baseline: the CPU oracle on a bounded sample of the same workload;
 * nested lines for the other configurations: the 64-pair batch (one graph
   launch, and the same pairs run one after another), the 160^3 speckle image
-  registration, and time-to-Dice of the learned proposal over 16 held-out
-  pairs.
+  registration, time-to-Dice of the learned proposal over 16 held-out pairs,
+  and the exhaustive-search baseline on the headline pair.
 """
 
 from __future__ import annotations
@@ -227,6 +227,26 @@ def gather_probe_run(reg, K, seed):
                                  f"one {K}-iteration registration; gather_frac = probe time / production time"}
 
 
+def exhaustive_run(reg, prm, V, smc_ms, smc_score, g=7):
+    """The exhaustive-search baseline (EX) on the same pair: every point of a
+    g^6 grid over the limits box scored once, argmax reported; timed beside
+    one SMC registration (context for the EX-versus-filter comparison of
+    Table 4)."""
+    import numpy as np
+    import torch
+    lim, x0 = np.array(prm["limit"]), np.array(prm["x0"])
+    lo, step = x0 - lim, 2.0 * lim / (g - 1)
+    reg.exhaustive(lo, step, [g] * 6)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = reg.exhaustive(lo, step, [g] * 6)
+    ms = (time.perf_counter() - t0) * 1e3
+    n = g ** 6
+    return {"grid": f"{g}^6 = {n} transforms over x0 +- limit", "ms": ms, "evals_per_s": float(n) * V / (ms * 1e-3),
+            "best_score": r["score"], "smc_final_score": smc_score, "smc_ms_per_registration": smc_ms,
+            "ex_over_smc_time": ms / smc_ms}
+
+
 def lv224(inp, args):
     import torch
 
@@ -271,10 +291,11 @@ def lv224(inp, args):
     reg.profile(False)
     launch_ms = prof["score_ms"] / max(1, prof["score_launches"])
     probe = None if args.no_gather_probe else gather_probe_run(reg, K, 77)
+    ex = None if args.no_exhaustive else exhaustive_run(reg, prm, V, wall * 1e3 / args.steps, est["score"])
     tuning = reg.tuning()
     reg.close()
     evals = float(N) * V * K * args.steps
-    return dict(wall=wall, evals=evals, est=est, N=N, K=K, V=V, F=F, tuning=tuning, prm=prm,
+    return dict(wall=wall, evals=evals, est=est, N=N, K=K, V=V, F=F, tuning=tuning, prm=prm, exhaustive=ex,
                 roofline=roofline("k_score_mask (warp-and-score, nearest, Dice counts)", OPS_PER_EVAL_MASK,
                                   float(N + 1) * V, launch_ms, prof["score_launches"], GATHER_BYTES_MASK, PMC_MASK,
                                   probe),
@@ -500,6 +521,7 @@ def main():
     ap.add_argument("--no-speckle", action="store_true", help="skip the nested speckle160 line")
     ap.add_argument("--speckle-steps", type=int, default=3)
     ap.add_argument("--no-gather-probe", action="store_true")
+    ap.add_argument("--no-exhaustive", action="store_true", help="skip the exhaustive-search line")
     ap.add_argument("--mask-tuning", default=None,
                     help="particles_per_group,tile_depth of the lv224 mask launch (default: the library's)")
     ap.add_argument("--image-tuning", default=DEFAULT_IMAGE_TUNING,
@@ -565,6 +587,8 @@ def main():
         "roofline": dict(h["roofline"], filter_ms_per_launch=h["filter_ms"]),
         "final_score": h["est"]["score"],
     }
+    if h["exhaustive"] is not None:
+        line["exhaustive"] = h["exhaustive"]
     if not args.no_speckle:
         line["speckle160"] = speckle160(inp, args)
     if not args.no_batch:
