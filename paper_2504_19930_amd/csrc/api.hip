@@ -377,9 +377,19 @@ smc_status launch_prior(smc_ctx *c) {
 
 // Mask contexts: item lists large enough for a filter launch (N + 1
 // particles) under the current tuning; smaller buffers are freed.
+// Every filter launch must fit one grid (masks and images alike).
+smc_status check_items(const smc_ctx *c) {
+    const uint64_t items = score_items_for(c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true));
+    if (items > kMaxScoreItems)
+        return fail(SMC_EINVAL, "%llu work items per scoring launch exceed %llu: use deeper tiles or fewer particles",
+                    (unsigned long long)items, (unsigned long long)kMaxScoreItems);
+    return SMC_OK;
+}
+
 smc_status ensure_items(smc_ctx *c) {
-    if (c->mode != kModeMask) return SMC_OK;
     smc_status st;
+    if ((st = check_items(c)) != SMC_OK) return st;
+    if (c->mode != kModeMask) return SMC_OK;
     if (!c->item_counters && (st = c->alloc(&c->item_counters, kItemCounterWords)) != SMC_OK) return st;
     const uint64_t need = score_items_for(c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true));
     if (need <= c->item_cap) return SMC_OK;
@@ -1006,6 +1016,16 @@ smc_status smc_set_tuning(smc_ctx *c, int32_t layout, int32_t pt, int32_t tile_d
     smc_status st;
     if ((st = c->check_sticky()) != SMC_OK) return st;
     if ((st = set_device(c)) != SMC_OK) return c->mark(st);
+    {
+        // refuse a tuning whose launches would not fit one grid, leaving the context as it was
+        const int old_pt = c->pt, old_z = c->zchunk;
+        if (pt >= 0) c->pt = pt;
+        if (tile_depth > 0) c->zchunk = tile_depth;
+        st = check_items(c);
+        c->pt = old_pt;
+        c->zchunk = old_z;
+        if (st != SMC_OK) return st;
+    }
     if (layout >= 0) {
         if (c->mode == kModeImageTrilinear && !layout_fits(layout, c->sn))
             return fail(SMC_EINVAL, "layout %d cannot address a %d x %d x %d source (packed size >= 4 GiB or "

@@ -60,6 +60,9 @@ struct ScoreLaunch {
     uint64_t item_cap = 0;
 };
 constexpr uint32_t kItemCounterWords = 512;
+// Most work items (tiles x particle groups) one scoring launch takes: a grid
+// dimension of signed 32-bit size.
+constexpr uint64_t kMaxScoreItems = 0x7FFFFFFFull;
 // Items (tiles x particle groups) of a launch of L's shape with np particles.
 uint64_t score_items_for(const ScoreLaunch &L);
 

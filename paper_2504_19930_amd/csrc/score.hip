@@ -1370,11 +1370,19 @@ int score_vmode(const ScoreLaunch &L) {
     return make_args(L, 8, &chunks).vmode;
 }
 
-void score_grid(const ScoreLaunch &L, dim3 *grid, dim3 *block) {
+// Work items (tiles x particle groups) of a launch, in 64 bits.
+uint64_t score_items64(const ScoreLaunch &L) {
     int chunks;
     const int pt = score_pt_supported(L.pt) ? L.pt : 8;
     const KArgs a = make_args(L, pt, &chunks);
-    *grid = dim3((unsigned)(a.tiles_x * a.tiles_y * chunks) * ((L.np + pt - 1) / pt), 1, 1);
+    return (uint64_t)a.tiles_x * (uint64_t)a.tiles_y * (uint64_t)chunks * (uint64_t)((L.np + pt - 1) / pt);
+}
+
+// A one-dimensional grid of one workgroup per item; grid.x = 0 (no launch
+// possible) when the items exceed a grid dimension.
+void score_grid(const ScoreLaunch &L, dim3 *grid, dim3 *block) {
+    const uint64_t items = score_items64(L);
+    *grid = dim3(items <= kMaxScoreItems ? (unsigned)items : 0u, 1, 1);
     *block = dim3(kThreads, 1, 1);
 }
 
@@ -1435,11 +1443,7 @@ hipError_t launch_mask_items(const ScoreLaunch &L, int pt, const KArgs &a, uint3
 
 }  // namespace
 
-uint64_t score_items_for(const ScoreLaunch &L) {
-    dim3 grid, block;
-    score_grid(L, &grid, &block);
-    return (uint64_t)grid.x * grid.y;
-}
+uint64_t score_items_for(const ScoreLaunch &L) { return score_items64(L); }
 
 hipError_t launch_score(const ScoreLaunch &L, hipStream_t s) {
     if (L.np == 0) return hipSuccess;
@@ -1448,6 +1452,7 @@ hipError_t launch_score(const ScoreLaunch &L, hipStream_t s) {
     const KArgs a = make_args(L, pt, &chunks);
     dim3 grid, block;
     score_grid(L, &grid, &block);
+    if (grid.x == 0) return hipErrorInvalidConfiguration;
     if (uses_item_lists(L, grid.x)) return launch_mask_items(L, pt, a, grid.x, false, 0u, nullptr, s);
     ScoreKernel k = pt == 4 ? pick<4>(L) : (pt == 16 ? pick<16>(L) : pick<8>(L));
     hipLaunchKernelGGL(k, grid, block, 0, s, a);
@@ -1618,6 +1623,7 @@ hipError_t launch_gather_probe(const ScoreLaunch &L, uint32_t key, uint32_t *out
     const KArgs a = make_args(L, pt, &chunks);
     dim3 grid, block;
     score_grid(L, &grid, &block);
+    if (grid.x == 0) return hipErrorInvalidConfiguration;
     // the same schedule as the production launch (culled item lists or grid)
     if (uses_item_lists(L, grid.x)) return launch_mask_items(L, pt, a, grid.x, true, key, out, s);
     ScoreKernel k = pt == 4 ? probe_kernel<4>(L) : (pt == 16 ? probe_kernel<16>(L) : probe_kernel<8>(L));

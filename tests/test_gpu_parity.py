@@ -597,3 +597,25 @@ def test_fov_sentinel_and_fallback_exact(smc, orc):
     for layout in ("pairx", "quadxy", "oct", "octtile", "lerp", "raw"):
         r.tune(layout, 4, 32)
         assert np.array_equal(r.evaluate(x), want), layout
+
+
+def test_work_items_beyond_one_grid_are_refused(smc):
+    """A tuning whose scoring launch would need more than 2^31 - 1 work items
+    (tiles x particle groups) is refused with SMC_EINVAL instead of launching a
+    truncated grid; the context keeps its previous tuning and still runs."""
+    import torch
+    nx, ny, nz = 1024, 512, 64
+    src = torch.zeros((nz, ny, nx), dtype=torch.uint8, device="cuda")
+    src[20:44, 200:300, 400:600] = 1
+    tgt = src.clone()
+    prm = config.default_params("dice", 65535, 1, 5.0, 2.0)
+    r = smc.Registration(src, tgt, prm)
+    before = r.tuning()
+    # 32 x 64 tiles per slice x 64 slices x 16384 groups = 2^31 items at depth 1
+    with pytest.raises(smc.SmcError) as e:
+        r.tune(None, 4, 1)
+    assert e.value.status == smc.SMC_EINVAL and "work items" in str(e.value)
+    assert r.tuning() == before
+    r.run()
+    assert r.estimate()["score"] > 0.5
+    r.close()
