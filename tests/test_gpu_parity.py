@@ -619,3 +619,36 @@ def test_work_items_beyond_one_grid_are_refused(smc):
     r.run()
     assert r.estimate()["score"] > 0.5
     r.close()
+
+
+def test_gather_probe_leaves_the_filter_alone(smc):
+    """smc_gather_probe times its probe and the scoring launch on the current
+    particle set without touching the filter: a registration probed before
+    every iteration ends exactly as one that was not; image contexts in the
+    one-gather layouts are supported, the MI score is refused."""
+    pair = synth.shell_pair(seed=3, side=48)
+    prm = config.default_params("dice", 256, 4, 15.0, 5.0, seed=9)
+    a, b = _reg(smc, pair, prm), _reg(smc, pair, prm)
+    for _ in range(4):
+        pm, sm = a.gather_probe(2)
+        assert pm > 0.0 and sm > 0.0
+        a.step(1)
+    b.run()
+    pa, pb = a.particles(), b.particles()
+    for k in ("states", "logw", "ancestors"):
+        assert np.array_equal(pa[k], pb[k]), k
+    assert np.array_equal(a.trace()["score"], b.trace()["score"])
+    a.close()
+    b.close()
+    sp = synth.speckle_pair(side=40, seed=5, trans=3.0)
+    for layout in ("oct", "octtile", "lerp"):
+        r = _reg(smc, sp, config.default_params("ncc", 64, 2, 20.0, 3.0), src_fov=sp["src_fov"])
+        r.tune(layout, 4, 256)
+        pm, sm = r.gather_probe(1)
+        assert pm > 0.0 and sm > 0.0
+        r.close()
+    r = _reg(smc, sp, config.default_params("mi", 64, 2, 20.0, 3.0), src_fov=sp["src_fov"])
+    with pytest.raises(smc.SmcError) as e:
+        r.gather_probe(1)
+    assert e.value.status == smc.SMC_EINVAL
+    r.close()
