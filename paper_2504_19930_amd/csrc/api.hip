@@ -181,7 +181,10 @@ struct smc_ctx {
     std::string sticky_msg;
     // smc_gather_probe checksum word
     uint32_t *probe_out = nullptr;
-    // masks: culled item lists of the filter's launches (capacity item_cap)
+    // masks: culled item lists of the filter's launches (capacity item_cap),
+    // sized for launches of items_np particles (a frame pair's context scores
+    // the particles of the context it belongs to)
+    uint32_t items_np = 0;
     void *items = nullptr;
     uint32_t *item_counters = nullptr;
     uint64_t item_cap = 0;
@@ -391,7 +394,9 @@ smc_status ensure_items(smc_ctx *c) {
     if ((st = check_items(c)) != SMC_OK) return st;
     if (c->mode != kModeMask) return SMC_OK;
     if (!c->item_counters && (st = c->alloc(&c->item_counters, kItemCounterWords)) != SMC_OK) return st;
-    const uint64_t need = score_items_for(c->score_launch(c->f.words, c->f.sums, 0, c->f.n + 1, true));
+    const uint32_t np = std::max(c->f.n + 1, c->items_np);
+    const uint64_t need = score_items_for(c->score_launch(c->f.words, c->f.sums, 0, np, true));
+    if (need > kMaxScoreItems) return SMC_OK;  // such launches run as a grid (and are refused there)
     if (need <= c->item_cap) return SMC_OK;
     if (c->items) {
         if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(SMC_EDEVICE, "stream sync failed");
@@ -1002,6 +1007,7 @@ smc_status smc_set_frames(smc_ctx *c, uint32_t n_extra, const smc_volume *src_fr
             return fail(st, "frame %u: %s", q + 1, msg.c_str());
         }
         c->frames.push_back(fr);
+        fr->items_np = c->f.n + 1;  // it scores this context's particles
         if ((st = smc_set_tuning(fr, c->layout, c->pt, c->zchunk)) != SMC_OK) return c->mark(st);
     }
     pool_frame_constants(c);

@@ -17,6 +17,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "internal.h"
 
@@ -1393,15 +1395,23 @@ __global__ __launch_bounds__(kThreads) void k_probe_mask_items(const KArgs a, co
                                                                const uint32_t *counts, uint32_t *take,
                                                                uint32_t total, uint32_t key, uint32_t *out);
 
-// Resident workgroups of a persistent kernel on the current device.
+// Resident workgroups of a persistent kernel on the current device (cached
+// per device and kernel; the occupancy query is made once).
 int persistent_blocks(const void *kernel) {
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_pair(dev, kernel);
+    const auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int cus = 0, per_cu = 0;
+    if (dev < 0 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         cus = 256;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || per_cu < 1)
         per_cu = 4;
-    return cus * per_cu;
+    return cache[key] = cus * per_cu;
 }
 
 template <int PT>
@@ -1415,13 +1425,11 @@ hipError_t launch_mask_items_pt(const KArgs &a, uint32_t total, const ScoreLaunc
                        counts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (probe) {
-        static int blocks = 0;
-        if (!blocks) blocks = persistent_blocks(reinterpret_cast<const void *>(k_probe_mask_items<PT>));
+        const int blocks = persistent_blocks(reinterpret_cast<const void *>(k_probe_mask_items<PT>));
         hipLaunchKernelGGL(k_probe_mask_items<PT>, dim3(blocks), dim3(kThreads), 0, s, a, (const uint2 *)L.items,
                            (const uint32_t *)counts, take, total, key, out);
     } else {
-        static int blocks = 0;
-        if (!blocks) blocks = persistent_blocks(reinterpret_cast<const void *>(k_score_mask_items<PT>));
+        const int blocks = persistent_blocks(reinterpret_cast<const void *>(k_score_mask_items<PT>));
         hipLaunchKernelGGL(k_score_mask_items<PT>, dim3(blocks), dim3(kThreads), 0, s, a, (const uint2 *)L.items,
                            (const uint32_t *)counts, take, total);
     }
