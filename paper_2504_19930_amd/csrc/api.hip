@@ -712,31 +712,34 @@ smc_status smc_gather_probe(smc_ctx *c, uint32_t reps, double *probe_ms, double 
     if (!gather_probe_supported(L))
         return fail(SMC_EINVAL, "no gather probe for this score mode, layout or target FOV");
     hipEvent_t e0 = take_event(c), e1 = take_event(c);
-    if (!e0 || !e1) return fail(SMC_EDEVICE, "hipEventCreate failed");
+    if (!e0 || !e1) {
+        if (e0) c->ev_pool.push_back(e0);
+        if (e1) c->ev_pool.push_back(e1);
+        return fail(SMC_EDEVICE, "hipEventCreate failed");
+    }
     // one untimed launch of each, then reps timed launches; the key is never
     // matched (a checksum equal to it would only write probe_out)
     double t_probe = 0.0, t_score = 0.0;
-    for (uint32_t r = 0; r <= reps; ++r) {
-        HIP_TRY(hipEventRecord(e0, c->stream));
-        HIP_TRY(launch_gather_probe(L, 0xA5A5A5A5u, c->probe_out, c->stream));
-        HIP_TRY(hipEventRecord(e1, c->stream));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (r > 0) t_probe += ms;
-    }
-    for (uint32_t r = 0; r <= reps; ++r) {
-        HIP_TRY(launch_fill_u64(c->s_eval, 6ull * np, c->stream));
-        HIP_TRY(hipEventRecord(e0, c->stream));
-        HIP_TRY(launch_score(L, c->stream));
-        HIP_TRY(hipEventRecord(e1, c->stream));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (r > 0) t_score += ms;
-    }
-    c->ev_pool.push_back(e0);
+    auto time_one = [&](bool probe, double *acc) -> hipError_t {
+        for (uint32_t r = 0; r <= reps; ++r) {
+            hipError_t e = probe ? hipSuccess : launch_fill_u64(c->s_eval, 6ull * np, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess)
+                e = probe ? launch_gather_probe(L, 0xA5A5A5A5u, c->probe_out, c->stream) : launch_score(L, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) return e;
+            if (r > 0) *acc += ms;
+        }
+        return hipSuccess;
+    };
+    hipError_t e = time_one(true, &t_probe);
+    if (e == hipSuccess) e = time_one(false, &t_score);
+    c->ev_pool.push_back(e0);  // the events go back to the pool on every path
     c->ev_pool.push_back(e1);
+    if (e != hipSuccess) return fail(SMC_EDEVICE, "gather probe: %s", hipGetErrorString(e));
     if (probe_ms) *probe_ms = t_probe / reps;
     if (score_ms) *score_ms = t_score / reps;
     return SMC_OK;

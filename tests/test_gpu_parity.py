@@ -231,6 +231,13 @@ def test_degenerate_sizes(smc, orc):
     st = smc.lib().smc_estimate(r.ctx, None, None, None, None)
     assert st == smc.SMC_ENOOVERLAP and "overlap" in smc.lib().smc_last_error().decode()
     assert not _reg(smc, spk, config.default_params("ncc", 16, 2, 10.0, 2.0, seed=1)).run()["no_overlap"]
+    # an empty source mask (its bounding box is empty: the filter's mask launches cull
+    # every item) and an empty target mask: Dice 0 throughout, as in the oracle
+    empty = dict(src=np.zeros_like(pair["src"]), tgt=pair["tgt"])
+    r, o = _compare_runs(smc, orc, empty, config.default_params("dice", 40, 3, 15.0, 3.0, seed=4))
+    assert np.all(r.trace()["score"] == 0.0)
+    _compare_runs(smc, orc, dict(src=pair["src"], tgt=np.zeros_like(pair["tgt"])),
+                  config.default_params("dice", 40, 3, 15.0, 3.0, seed=4))
 
 
 def test_stepwise_equals_single_call_and_state_roundtrip(smc, orc):
