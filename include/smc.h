@@ -272,7 +272,11 @@ void smc_destroy(smc_ctx *ctx);
  * (nx, ny, nz, spacing sx, sy, sz).  NEAREST copies the source byte; TRILINEAR
  * writes floor(v + 0.5); target voxels whose source position falls outside
  * the source grid get 0.  Frame f is read at src->data + f * src_frame_stride
- * and written at dst + f * dst_frame_stride (bytes).  src->fov is ignored. */
+ * and written at dst + f * dst_frame_stride (bytes).  src->fov is ignored.
+ * Asynchronous on hip_stream.  SMC_EINVAL for NULL pointers, non-finite
+ * matrix entries, an unknown interp, output dimensions outside 1..65535 or an
+ * output frame of 2^31 voxels or more, non-positive spacing, n_frames outside
+ * 1..65535 or frame strides smaller than a frame; SMC_EDEVICE if the launch fails. */
 smc_status warp_apply(const smc_volume *src, const double mat3x4[12], int32_t interp, uint8_t *dst,
                       int32_t nx, int32_t ny, int32_t nz, double sx, double sy, double sz, uint32_t n_frames,
                       int64_t src_frame_stride, int64_t dst_frame_stride, void *hip_stream);

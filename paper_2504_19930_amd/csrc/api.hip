@@ -1246,6 +1246,7 @@ smc_status warp_apply(const smc_volume *src, const double mat3x4[12], int32_t in
     if (!(sx > 0 && sy > 0 && sz > 0)) return fail(SMC_EINVAL, "output spacing must be positive");
     if (n_frames < 1 || n_frames > 65535) return fail(SMC_EINVAL, "n_frames must be in 1..65535");
     const int64_t vs = (int64_t)src->nx * src->ny * src->nz, vt = (int64_t)nx * ny * nz;
+    if (vt >= ((int64_t)1 << 31)) return fail(SMC_EINVAL, "output frames of 2^31 voxels or more");
     if (n_frames > 1 && (src_frame_stride < vs || dst_frame_stride < vt))
         return fail(SMC_EINVAL, "frame strides smaller than a frame");
     const double ts[3] = {sx, sy, sz}, ss[3] = {src->sx, src->sy, src->sz};

@@ -8,6 +8,23 @@
 
 namespace smc {
 
+// floor and convert in one instruction (exact for the non-negative
+// coordinates whose results are used)
+__device__ __forceinline__ uint32_t floor_u32(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return (uint32_t)r;
+}
+
+// a * b + c on the low 24 bits of a and b, as one instruction (the compiler
+// otherwise forms two multiplies and a three-way add); b is uniform across
+// the wave (a stride) and is passed as a scalar operand.
+__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
 // Warp-and-score launch: particle range [p0, p0 + np) of `words`, sums
 // accumulated (atomically, exactly) into sums[6 * p].
 enum ScoreMode : int { kModeMask = 0, kModeImageTrilinear = 1, kModeImageNearest = 2 };

@@ -230,23 +230,6 @@ __device__ __forceinline__ void stage_target(const KArgs &a, const Tile &t, int 
     }
 }
 
-// floor and convert in one instruction (exact for the non-negative
-// coordinates whose results are used)
-__device__ __forceinline__ uint32_t floor_u32(float x) {
-    int r;
-    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
-    return (uint32_t)r;
-}
-
-// a * b + c on the low 24 bits of a and b, as one instruction (the compiler
-// otherwise forms two multiplies and a three-way add); b is uniform across
-// the wave (a stride) and is passed as a scalar operand.
-__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
-    uint32_t r;
-    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
-    return r;
-}
-
 // The same with a constant b.
 __device__ __forceinline__ uint32_t mad_u24v(uint32_t a, uint32_t b, uint32_t c) { return __umul24(a, b) + c; }
 
