@@ -35,9 +35,10 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // Word 3 of a raw buffer resource on gfx9-family GPUs (32-bit data format,
 // untyped loads; out-of-range offsets read zero and writes are dropped).
 constexpr int kBufferWord3 = 0x00020000;
-// LDS bytes a staged workgroup may take: three workgroups per CU with 16-slice
-// tiles (whose registers allow three), four with 8-slice tiles.
-constexpr uint32_t kStageBudget16 = 52u * 1024u, kStageBudget8 = 40u * 1024u;
+// LDS bytes of a staged workgroup's source box: with its output tile (4 or 2
+// KB) three workgroups per CU for 16-slice tiles (whose registers allow
+// three), four for 8-slice tiles.
+constexpr uint32_t kStageBudget16 = 48u * 1024u, kStageBudget8 = 36u * 1024u;
 // Source-box rows of at most four 16-byte chunks; row passes a thread keeps
 // in flight while staging.
 constexpr uint32_t kChunks = 4;
@@ -103,9 +104,38 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const uint8_t *p, ui
 // source read them, with fractions 0), then the box: rows of P bytes, slices
 // of Pz bytes, one more row and slice for the +1 taps.  The box of frame f + 1
 // is loaded into registers while frame f is computed.
+// Write one frame's output tile, assembled in LDS as ZC slices x kWY rows x
+// kWX bytes, with 16-byte stores: thread t takes half t % 2 of row t / 2
+// (rows past the target, and the tail of a row past its end, are skipped; a
+// row whose 16 bytes do not all lie inside, or outputs whose rows are not
+// 4-byte aligned, are written byte by byte).
 template <int ZC>
-__global__ __launch_bounds__(256) void k_warp_trilinear_lds(const WArgs a) {
+__device__ __forceinline__ void store_tile(const uint8_t *tile, const WArgs &a, const WTile &t, int f) {
+    static_assert(kWX == 32, "two 16-byte halves per tile row");
+    const uint32_t plane = (uint32_t)a.tn0 * (uint32_t)a.tn1;
+    const __amdgpu_buffer_rsrc_t rd = buffer_of(a.dst + a.dst_stride * f, plane * (uint32_t)a.tn2);
+    const int x = t.x0 + 16 * (int)(threadIdx.x % 2u);
+    const bool vec = a.tn0 % 4 == 0;
+#pragma unroll
+    for (int r = (int)(threadIdx.x / 2u); r < ZC * kWY; r += 128) {
+        const int k = t.k0 + r / kWY, j = t.y0 + r % kWY;
+        if (k >= t.k1 || j >= a.tn1 || x >= a.tn0) continue;
+        const u32x4 v = *(const u32x4 *)(tile + r * kWX + (x - t.x0));
+        const uint32_t o = (uint32_t)x + (uint32_t)a.tn0 * (uint32_t)j + plane * (uint32_t)k;
+        if (vec && x + 16 <= a.tn0) {
+            __builtin_amdgcn_raw_buffer_store_b128(v, rd, o, 0, 0);
+        } else {
+            for (int b = 0; b < 16 && x + b < a.tn0; ++b)
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(v[b / 4] >> (8 * (b % 4))), rd, o + (uint32_t)b, 0, 0);
+        }
+    }
+}
+
+template <int ZC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ZC == 16 ? 3 : 4)))
+void k_warp_trilinear_lds(const WArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    __shared__ __attribute__((aligned(16))) uint8_t tile[ZC * kWY * kWX];
     const WTile t = warp_tile(a);
     const uint32_t sn0 = (uint32_t)a.sn0, sn01 = (uint32_t)a.sn0 * (uint32_t)a.sn1;
     const uint32_t nbytes = sn01 * (uint32_t)a.sn2;
@@ -156,7 +186,6 @@ __global__ __launch_bounds__(256) void k_warp_trilinear_lds(const WArgs a) {
     // the thread's column and, per slice, its LDS index and fractions
     int i, j;
     warp_column(t, i, j);
-    const bool col = i < a.tn0 && j < a.tn1;
     const float fi = (float)i, fj = (float)j;
     const float mx = fmaf(a.w[1], fj, fmaf(a.w[0], fi, a.w[3]));
     const float my = fmaf(a.w[5], fj, fmaf(a.w[4], fi, a.w[7]));
@@ -186,8 +215,8 @@ __global__ __launch_bounds__(256) void k_warp_trilinear_lds(const WArgs a) {
         }
     }
     if (threadIdx.x == 0) *(u32x4 *)lds = u32x4{0u, 0u, 0u, 0u};
-    const uint32_t plane = (uint32_t)a.tn0 * (uint32_t)a.tn1;
-    const uint32_t o0 = (uint32_t)i + (uint32_t)a.tn0 * (uint32_t)j;
+    // the thread's byte of the output tile in slice 0
+    const uint32_t tl = (uint32_t)(j - t.y0) * kWX + (uint32_t)(i - t.x0);
 
     u32x4 v[kStagePasses];
     auto load_box = [&](int f) {
@@ -213,13 +242,12 @@ __global__ __launch_bounds__(256) void k_warp_trilinear_lds(const WArgs a) {
     const int f0 = t.frame * (int)a.fg, f1 = min(f0 + (int)a.fg, (int)a.frames);
     load_box(f0);
     for (int f = f0; f < f1; ++f) {
-        __syncthreads();  // every thread is done with frame f - 1's box
+        __syncthreads();  // every thread is done with frame f - 1's box and tile
 #pragma unroll
         for (int u = 0; u < kStagePasses; ++u)
             if (gl[u] != 0u) *(u32x4 *)(lds + gl[u]) = v[u];
         __syncthreads();
         if (f + 1 < f1) load_box(f + 1);
-        const __amdgpu_buffer_rsrc_t rd = buffer_of(a.dst + a.dst_stride * f, plane * (uint32_t)a.tn2);
 #pragma unroll
         for (int q = 0; q < ZC; ++q) {
             // byte taps (2-byte LDS reads at odd addresses are far slower)
@@ -230,21 +258,22 @@ __global__ __launch_bounds__(256) void k_warp_trilinear_lds(const WArgs a) {
             const float x01 = fmaf(fx[q], v5 - v4, v4), x11 = fmaf(fx[q], v7 - v6, v6);
             const float y0 = fmaf(fy[q], x10 - x00, x00), y1 = fmaf(fy[q], x11 - x01, x01);
             // lerps of bytes stay within [0, 255]: no upper clamp needed
-            const uint32_t val = floor_u32(fmaf(fz[q], y1 - y0, y0) + 0.5f);
-            if (col && t.k0 + q < t.k1)
-                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)val, rd, o0, (int)(plane * (uint32_t)(t.k0 + q)), 0);
+            tile[q * kWY * kWX + tl] = (uint8_t)floor_u32(fmaf(fz[q], y1 - y0, y0) + 0.5f);
         }
+        __syncthreads();
+        store_tile<ZC>(tile, a, t, f);
     }
 }
 
 // Nearest neighbour: one workgroup per tile and group of frames, looping over
-// them two at a time (every load of both frames issued before the stores).
+// them two at a time: every gather of both frames issued, the bytes placed in
+// two LDS output tiles, then the tiles written with 16-byte stores.
 template <int ZC>
-__global__ __launch_bounds__(256) void k_warp_nearest(const WArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_warp_nearest(const WArgs a) {
+    __shared__ __attribute__((aligned(16))) uint8_t tile[2][ZC * kWY * kWX];
     const WTile t = warp_tile(a);
     int i, j;
     warp_column(t, i, j);
-    if (i >= a.tn0 || j >= a.tn1) return;
     const uint32_t sn0 = (uint32_t)a.sn0, sn01 = (uint32_t)a.sn0 * (uint32_t)a.sn1;
     const uint32_t nbytes = sn01 * (uint32_t)a.sn2;
     const float fi = (float)i, fj = (float)j;
@@ -265,8 +294,8 @@ __global__ __launch_bounds__(256) void k_warp_nearest(const WArgs a) {
                         (__float_as_uint(uz) < nzb);
         off[q] = in ? mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, floor_u32(ux))) : nbytes;
     }
-    const uint32_t plane = (uint32_t)a.tn0 * (uint32_t)a.tn1;
-    const uint32_t o0 = (uint32_t)i + (uint32_t)a.tn0 * (uint32_t)j;
+    // the thread's byte of an output tile in slice 0
+    const uint32_t tl = (uint32_t)(j - t.y0) * kWX + (uint32_t)(i - t.x0);
     const int f0 = t.frame * (int)a.fg, f1 = min(f0 + (int)a.fg, (int)a.frames);
     for (int f = f0; f < f1; f += 2) {
         const bool two = f + 1 < f1;
@@ -278,19 +307,15 @@ __global__ __launch_bounds__(256) void k_warp_nearest(const WArgs a) {
             v0[q] = __builtin_amdgcn_raw_buffer_load_b8(r0, off[q], 0, 0);
             v1[q] = __builtin_amdgcn_raw_buffer_load_b8(r1, off[q], 0, 0);
         }
-        const __amdgpu_buffer_rsrc_t d0 = buffer_of(a.dst + a.dst_stride * f, plane * (uint32_t)a.tn2);
+        __syncthreads();  // the tiles of the previous pair are written out
 #pragma unroll
-        for (int q = 0; q < ZC; ++q)
-            if (t.k0 + q < t.k1)
-                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v0[q], d0, o0, (int)(plane * (uint32_t)(t.k0 + q)), 0);
-        if (two) {
-            const __amdgpu_buffer_rsrc_t d1 = buffer_of(a.dst + a.dst_stride * (f + 1), plane * (uint32_t)a.tn2);
-#pragma unroll
-            for (int q = 0; q < ZC; ++q)
-                if (t.k0 + q < t.k1)
-                    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v1[q], d1, o0,
-                                                         (int)(plane * (uint32_t)(t.k0 + q)), 0);
+        for (int q = 0; q < ZC; ++q) {
+            tile[0][q * kWY * kWX + tl] = (uint8_t)v0[q];
+            tile[1][q * kWY * kWX + tl] = (uint8_t)v1[q];
         }
+        __syncthreads();
+        store_tile<ZC>(tile[0], a, t, f);
+        if (two) store_tile<ZC>(tile[1], a, t, f + 1);
     }
 }
 
