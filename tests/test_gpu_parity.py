@@ -294,16 +294,17 @@ def _rot_matrix(axis, deg, centre, shift):
 
 # (source shape xyz, target shape xyz, target spacing, matrix); source spacing 1
 _WARP_CASES = {
-    # staged, 32-slice tiles: every sample on the grid, the last index's +1
-    # taps outside the source
+    # trilinear staged, 16-slice tiles: every sample on the grid, the last
+    # index's +1 taps outside the source
     "identity": ((44, 36, 40), (70, 19, 37), 1.0, np.hstack([np.eye(3), np.zeros((3, 1))])),
     "integer_shift": ((44, 36, 40), (70, 19, 37), 1.0, np.hstack([np.eye(3), [[3.0], [-2.0], [1.0]]])),
     "half_voxel_shift": ((44, 36, 40), (70, 19, 37), 1.0, np.hstack([np.eye(3), [[0.5], [-0.5], [0.5]]])),
     # staged, 16- and 8-slice tiles
     "rotation_7deg": ((44, 36, 40), (70, 19, 37), 1.0, _rot_matrix((0.3, -0.5, 0.8), 7.0, (22, 18, 20), (1.3, -0.7, 2.2))),
+    "rotation_20deg": ((44, 36, 40), (70, 19, 37), 1.0, _rot_matrix((1.0, 0.4, -0.6), 20.0, (22, 18, 20), (0.4, 0.9, -1.1))),
+    # direct: boxes too large to stage (a wide rotation, a coarse target
+    # grid), rows that are not 4-byte aligned, coordinates beyond 2^20
     "rotation_30deg": ((44, 36, 40), (70, 19, 37), 1.0, _rot_matrix((1.0, 0.4, -0.6), 30.0, (22, 18, 20), (0.4, 0.9, -1.1))),
-    # direct: a box too large to stage (coarse target grid), rows that are
-    # not 4-byte aligned, coordinates beyond 2^20
     "coarse_45deg": ((44, 36, 40), (30, 21, 17), 2.5, _rot_matrix((0.0, 0.0, 1.0), 45.0, (22, 18, 20), (0.3, 0.2, 0.1))),
     "odd_rows": ((43, 36, 40), (70, 19, 37), 1.0, _rot_matrix((0.3, -0.5, 0.8), 7.0, (22, 18, 20), (1.3, -0.7, 2.2))),
     "far_away": ((44, 36, 40), (70, 19, 37), 1.0, np.hstack([np.eye(3), [[3.0e6], [0.0], [0.0]]])),
