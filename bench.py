@@ -13,7 +13,9 @@ value = N x V x K x steps / wall time (particle x voxel evaluations per
 second, V the nominal target grid).  The JSON line also carries
 
 * roofline: the dominant kernel (mask warp-and-score), timed live with HIP
-  events on the library's stream, against the published FP32 vector peak;
+  events on the library's stream, against the published FP32 vector peak,
+  on the particle x voxel pairs it evaluates (tile culling skips the pairs
+  it proves add nothing; the library counts both);
   its gather probe (the same grid, coordinates and source loads and nothing
   else) timed on the particle sets of a real registration;
 * cpu_baseline: the CPU oracle on a bounded sample of the same workload;
@@ -130,6 +132,26 @@ def roofline(kernel, ops_per_eval, evals_per_launch, launch_ms, launches, gather
          "gather_path": pmc_gather_path(pmc_path, launch_ms)}
     if probe is not None:
         r.update(probe)
+    return r
+
+
+def mask_roofline(launch_ms, launches, work, N, V, probe):
+    """The mask kernel's roofline on the work its launches did: tile culling
+    proves that a particle adds nothing to a tile whose image reaches no
+    occupied source cell and skips it, so `achieved` counts the evaluated
+    particle x voxel pairs only (the headline value counts every pair of the
+    target grid, as the sums do)."""
+    # the counters also cover the final estimate's own one-particle scoring:
+    # per launch, the evaluated fraction of the launch's N + 1 particles
+    grid = float(N + 1) * V
+    frac_eval = work["evaluated"] / work["covered"] if work["covered"] else 1.0
+    evaluated, covered = frac_eval * grid, grid
+    r = roofline("k_score_mask (warp-and-score, nearest, Dice counts)", OPS_PER_EVAL_MASK, evaluated, launch_ms,
+                 launches, GATHER_BYTES_MASK, PMC_MASK, probe)
+    r.update({"evals_per_launch_covered": covered, "evaluated_fraction": frac_eval,
+              "evals_note": "evals_per_launch = particle x voxel pairs evaluated per launch (the culled ones "
+                            "excluded): the fraction the cull pre-pass counted over the timed registrations times "
+                            "the launch's (N + 1) x V pairs"})
     return r
 
 
@@ -281,6 +303,7 @@ def lv224(inp, args):
     log(f"lv224: timing {args.steps} steps ...")
     reg.profile(True)
     reg.profile_read()
+    reg.profile_work()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
@@ -288,6 +311,7 @@ def lv224(inp, args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = reg.profile_read()
+    work = reg.profile_work()
     reg.profile(False)
     launch_ms = prof["score_ms"] / max(1, prof["score_launches"])
     probe = None if args.no_gather_probe else gather_probe_run(reg, K, 77)
@@ -296,9 +320,7 @@ def lv224(inp, args):
     reg.close()
     evals = float(N) * V * K * args.steps
     return dict(wall=wall, evals=evals, est=est, N=N, K=K, V=V, F=F, tuning=tuning, prm=prm, exhaustive=ex,
-                roofline=roofline("k_score_mask (warp-and-score, nearest, Dice counts)", OPS_PER_EVAL_MASK,
-                                  float(N + 1) * V, launch_ms, prof["score_launches"], GATHER_BYTES_MASK, PMC_MASK,
-                                  probe),
+                roofline=mask_roofline(launch_ms, prof["score_launches"], work, N, V, probe),
                 filter_ms=prof["filter_ms"] / max(1, prof["filter_launches"]))
 
 

@@ -264,6 +264,16 @@ smc_status smc_profile(smc_ctx *ctx, int32_t enable);
 smc_status smc_profile_read(smc_ctx *ctx, double *score_ms, uint64_t *score_launches, double *filter_ms,
                             uint64_t *filter_launches);
 
+/* Work of the filter's culled mask launches (masks, Methods: the Dice
+ * evaluation; image contexts report 0).  Tile culling skips a particle for a
+ * target tile when no sample of the tile's image can read an "on" source
+ * voxel: the image's box misses the source mask's bounding box or covers only
+ * unoccupied 4^3-voxel cells.  Returns, since the previous call (or
+ * smc_init), the particle x voxel pairs those launches evaluated and the
+ * pairs they covered (the skipped ones included), and clears both.  Syncs
+ * the context's stream.  Outputs may be NULL. */
+smc_status smc_profile_work(smc_ctx *ctx, uint64_t *evaluated, uint64_t *covered);
+
 /* Free everything the context owns (after syncing its stream).  NULL is a no-op. */
 void smc_destroy(smc_ctx *ctx);
 

@@ -26,7 +26,7 @@ ROTATIONS = {"box": 0, "wide": 1}
 # every symbol include/smc.h declares
 EXPORTS = ("smc_init", "smc_reset", "smc_step", "smc_estimate", "smc_get_particles", "smc_trace",
            "smc_evaluate", "smc_set_particles", "smc_get_state", "smc_set_state", "smc_destroy",
-           "warp_apply", "smc_last_error", "smc_version", "smc_profile", "smc_profile_read",
+           "warp_apply", "smc_last_error", "smc_version", "smc_profile", "smc_profile_read", "smc_profile_work",
            "smc_set_tuning", "smc_get_tuning", "smc_batch_init", "smc_batch_set_seeds", "smc_batch_run",
            "smc_batch_pair", "smc_batch_destroy", "smc_cnn_create", "smc_cnn_set_params", "smc_cnn_get_params",
            "smc_cnn_input", "smc_cnn_read_input", "smc_cnn_forward", "smc_cnn_backward", "smc_cnn_step", "smc_cnn_destroy",
@@ -83,6 +83,7 @@ def lib():
             "warp_apply": [P(SmcVolume), vp, i32, vp, i32, i32, i32, dp, dp, dp, u32, i64, i64, vp],
             "smc_profile": [vp, i32],
             "smc_profile_read": [vp, vp, vp, vp, vp],
+            "smc_profile_work": [vp, vp, vp],
             "smc_set_tuning": [vp, i32, i32, i32],
             "smc_set_frames": [vp, u32, vp, vp],
             "smc_score_particles": [vp, vp, u32, vp],
@@ -273,6 +274,12 @@ def smc_profile(ctx, enable: bool):
     _check(lib().smc_profile(ctx, 1 if enable else 0))
 
 
+def smc_profile_work(ctx) -> dict:
+    ev, cov = C.c_uint64(), C.c_uint64()
+    _check(lib().smc_profile_work(ctx, C.cast(C.byref(ev), C.c_void_p), C.cast(C.byref(cov), C.c_void_p)))
+    return dict(evaluated=ev.value, covered=cov.value)
+
+
 def smc_profile_read(ctx) -> dict:
     sm, fm = C.c_double(), C.c_double()
     sn, fn = C.c_uint64(), C.c_uint64()
@@ -437,6 +444,11 @@ class Registration:
 
     def profile_read(self):
         return smc_profile_read(self.ctx)
+
+    def profile_work(self):
+        """Particle x voxel pairs the culled mask launches evaluated and
+        covered since the previous call."""
+        return smc_profile_work(self.ctx)
 
     def gather_probe(self, reps=1):
         """(probe ms, production ms) per launch on the current particle set."""

@@ -160,6 +160,8 @@ struct smc_ctx {
     uint32_t *src_bits = nullptr;  // masks: bitmap of the source's on bits
     int layout = kDefaultLayout, pt = kDefaultPT, zchunk = kDefaultZChunkMask;
     int32_t box_lo[3] = {1, 1, 1}, box_hi[3] = {-1, -1, -1};  // source mask bounding box (empty)
+    uint32_t *occ = nullptr;  // masks: summed-area table of the source's occupied cells (or none)
+    unsigned long long *work = nullptr;  // masks: pairs evaluated and covered by the culled launches
     void *packed[kLayouts] = {};
     uint64_t sentinel[kLayouts] = {};  // per packed layout: value marking elements outside the source FOV
     bool has_sentinel[kLayouts] = {};
@@ -238,6 +240,8 @@ struct smc_ctx {
         if (mode == kModeMask) {
             L.src = src_prep;
             L.src_bits = src_bits;
+            L.occ = L.cull_box ? occ : nullptr;
+            L.work = L.cull_box ? work : nullptr;
             L.src_ok = nullptr;
             L.tgt = tgt_prep;
             L.tgt_fov = nullptr;
@@ -555,6 +559,17 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
                 c->box_lo[d] = hb[d];
                 c->box_hi[d] = hb[3 + d];
             }
+        // occupancy of 4^3-voxel cells for the culled launches, when its table
+        // is modest (flat volumes would make its zero borders large)
+        if ((st = c->alloc(&c->work, kWorkSlots * kWorkSlotWords)) != SMC_OK) return bail(st);
+        if (launch_fill_u64(c->work, kWorkSlots * kWorkSlotWords, c->stream) != hipSuccess)
+            return bail(fail(SMC_EDEVICE, "work counter fill failed"));
+        const uint64_t ow = mask_occ_words(c->sn);
+        if (ow <= kOccMaxWords) {
+            if ((st = c->alloc(&c->occ, ow)) != SMC_OK) return bail(st);
+            if (launch_mask_occupancy(c->src_prep, c->sn, c->occ, c->stream) != hipSuccess)
+                return bail(fail(SMC_EDEVICE, "source mask occupancy launch failed"));
+        }
     }
 
     // exact per-volume sums -> statistics
@@ -1212,6 +1227,27 @@ smc_status smc_profile_read(smc_ctx *c, double *score_ms, uint64_t *score_n, dou
     if (score_n) *score_n = counts[0];
     if (filter_ms) *filter_ms = sums[1];
     if (filter_n) *filter_n = counts[1];
+    return SMC_OK;
+}
+
+smc_status smc_profile_work(smc_ctx *c, uint64_t *evaluated, uint64_t *covered) {
+    if (!c) return fail(SMC_EINVAL, "ctx is NULL");
+    smc_status st;
+    if ((st = set_device(c)) != SMC_OK) return st;
+    std::vector<unsigned long long> w(kWorkSlots * kWorkSlotWords, 0ull);
+    if (c->work) {
+        HIP_TRY(hipMemcpyAsync(w.data(), c->work, w.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                               c->stream));
+        HIP_TRY(launch_fill_u64(c->work, kWorkSlots * kWorkSlotWords, c->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    uint64_t ev = 0, cov = 0;
+    for (uint32_t q = 0; q < kWorkSlots; ++q) {
+        ev += w[q * kWorkSlotWords];
+        cov += w[q * kWorkSlotWords + 1];
+    }
+    if (evaluated) *evaluated = ev;
+    if (covered) *covered = cov;
     return SMC_OK;
 }
 

@@ -59,6 +59,13 @@ struct ScoreLaunch {
     bool cull_box;
     int32_t box_lo[3], box_hi[3];
     const uint32_t *src_bits = nullptr;  // mask: bitmap of the source's on bits (the filter's launches)
+    // mask, culled launches: summed-area table of the source's occupied cells
+    // (or nullptr: the bounding box alone)
+    const uint32_t *occ = nullptr;
+    // mask, culled item-list launches (or nullptr): kWorkSlots counter pairs,
+    // kWorkSlotWords apart; summed over the slots, word 0 counts the particle x
+    // voxel pairs evaluated, word 1 the pairs covered (the culled ones included)
+    unsigned long long *work = nullptr;
     const uint8_t *src_ok;    // image: corner-valid bytes (source FOV) or nullptr
     const uint8_t *tgt;       // mask: prepared bits; image: intensities
     const uint8_t *tgt_fov;   // image: target FOV or nullptr
@@ -144,6 +151,14 @@ hipError_t launch_mask_bbox(const uint8_t *prep, const int32_t n[3], int32_t *ou
 // bytes of the bitmap of a volume of shape n, and the packing launch.
 uint64_t mask_bits_bytes(const int32_t n[3]);
 hipError_t launch_pack_mask_bits(const uint8_t *prep, const int32_t n[3], uint32_t *out, hipStream_t s);
+// Occupancy of the prepared source mask's "on" bits over cells of
+// 2^kOccShift voxels a side, as a summed-area table with a zero first row,
+// column and slice: words of the table, and the building launches.
+constexpr int kOccShift = 2;
+constexpr uint64_t kOccMaxWords = 16ull << 20;  // 64 MB
+constexpr uint32_t kWorkSlots = 64, kWorkSlotWords = 16;
+uint64_t mask_occ_words(const int32_t n[3]);
+hipError_t launch_mask_occupancy(const uint8_t *prep, const int32_t n[3], uint32_t *sat, hipStream_t s);
 hipError_t launch_corner_valid(const uint8_t *fov, uint8_t *out, const int32_t n[3], hipStream_t s);
 // out[0..3] += (fov count, nonzero count, sum v, sum v^2) over the FOV
 hipError_t launch_volume_sums(const uint8_t *vol, const uint8_t *fov, int64_t n, unsigned long long *out,

@@ -209,6 +209,52 @@ __global__ void k_mask_bbox(const uint8_t *prep, int32_t nx, int32_t ny, int32_t
     }
 }
 
+// Occupancy of the source mask's on bits over cells of 2^kOccShift voxels a
+// side, as a summed-area table S[(z (cy + 1) + y) (cx + 1) + x] = number of
+// occupied cells with cell coordinates below (x, y, z) (a zero first row,
+// column and slice).  First the cells (one thread per table entry), then
+// prefix sums along x, y and z (one thread per line).
+__global__ void k_occ_cells(const uint8_t *prep, int32_t nx, int32_t ny, int32_t nz, int32_t cx, int32_t cy,
+                            int32_t cz, uint32_t *S) {
+    const int64_t X = cx + 1, XY = X * (cy + 1), n = XY * (cz + 1);
+    constexpr int kc = 1 << kOccShift;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t x = (int32_t)(q % X), y = (int32_t)((q / X) % (cy + 1)), z = (int32_t)(q / XY);
+        uint32_t on = 0u;
+        if (x > 0 && y > 0 && z > 0) {
+            const int32_t x0 = (x - 1) * kc, y0 = (y - 1) * kc, z0 = (z - 1) * kc;
+            for (int32_t k = z0; k < min(z0 + kc, nz) && !on; ++k)
+                for (int32_t j = y0; j < min(y0 + kc, ny) && !on; ++j)
+                    for (int32_t i = x0; i < min(x0 + kc, nx); ++i)
+                        if (prep[(int64_t)i + (int64_t)nx * (j + (int64_t)ny * k)] & 2u) {
+                            on = 1u;
+                            break;
+                        }
+        }
+        S[q] = on;
+    }
+}
+
+// Prefix sums of the table along one axis (0 = x, 1 = y, 2 = z).
+__global__ void k_occ_prefix(uint32_t *S, int32_t cx, int32_t cy, int32_t cz, int32_t axis) {
+    const int64_t X = cx + 1, Y = cy + 1, Z = cz + 1;
+    const int64_t len = axis == 0 ? X : axis == 1 ? Y : Z;
+    const int64_t step = axis == 0 ? 1 : axis == 1 ? X : X * Y;
+    const int64_t lines = X * Y * Z / len;
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < lines; l += (int64_t)gridDim.x * blockDim.x) {
+        // start of line l: the index with coordinate 0 along the axis
+        int64_t base;
+        if (axis == 0) base = l * X;
+        else if (axis == 1) base = (l / X) * X * Y + l % X;
+        else base = l;
+        uint32_t run = 0u;
+        for (int64_t t = 0; t < len; ++t) {
+            run += S[base + t * step];
+            S[base + t * step] = run;
+        }
+    }
+}
+
 unsigned blocks_for(int64_t n) {
     int64_t b = (n + 255) / 256;
     return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
@@ -235,6 +281,25 @@ hipError_t launch_pack_mask_bits(const uint8_t *prep, const int32_t n[3], uint32
 hipError_t launch_mask_bbox(const uint8_t *prep, const int32_t n[3], int32_t *out, hipStream_t s) {
     const int64_t tot = (int64_t)n[0] * n[1] * n[2];
     hipLaunchKernelGGL(k_mask_bbox, dim3(blocks_for(tot)), dim3(256), 0, s, prep, n[0], n[1], n[2], out);
+    return hipGetLastError();
+}
+
+uint64_t mask_occ_words(const int32_t n[3]) {
+    const uint64_t cx = ((uint64_t)n[0] + (1u << kOccShift) - 1) >> kOccShift;
+    const uint64_t cy = ((uint64_t)n[1] + (1u << kOccShift) - 1) >> kOccShift;
+    const uint64_t cz = ((uint64_t)n[2] + (1u << kOccShift) - 1) >> kOccShift;
+    return (cx + 1) * (cy + 1) * (cz + 1);
+}
+
+hipError_t launch_mask_occupancy(const uint8_t *prep, const int32_t n[3], uint32_t *sat, hipStream_t s) {
+    const int32_t c = 1 << kOccShift;
+    const int32_t cx = (n[0] + c - 1) / c, cy = (n[1] + c - 1) / c, cz = (n[2] + c - 1) / c;
+    hipLaunchKernelGGL(k_occ_cells, dim3(blocks_for((int64_t)mask_occ_words(n))), dim3(256), 0, s, prep, n[0], n[1],
+                       n[2], cx, cy, cz, sat);
+    const int64_t X = cx + 1, Y = cy + 1, Z = cz + 1;
+    const int64_t lines[3] = {Y * Z, X * Z, X * Y};
+    for (int32_t axis = 0; axis < 3; ++axis)
+        hipLaunchKernelGGL(k_occ_prefix, dim3(blocks_for(lines[axis])), dim3(256), 0, s, sat, cx, cy, cz, axis);
     return hipGetLastError();
 }
 

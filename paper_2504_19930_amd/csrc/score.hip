@@ -46,6 +46,12 @@ struct KArgs {
     // exact culling: a particle can add to the sums of a tile only if the
     // tile's image reaches the source-coordinate box [cull_lo, cull_hi]
     float cull_lo[3], cull_hi[3];
+    // masks, culled launches: and only if a source voxel the image can sample
+    // is on: summed-area table of occupied cells (nullptr: not used), its row
+    // and slice strides, and the largest voxel index per axis
+    const uint32_t *occ;
+    uint32_t ocx, ocxy;
+    float occ_hi[3];
     // source FOV validity of a trilinear sample: 0 none, 1 gather src_ok,
     // 2 packed elements equal to `sentinel` mark samples outside the FOV
     int32_t vmode;
@@ -164,16 +170,36 @@ __device__ __forceinline__ void box_centre(const int lo[3], const int hi[3], flo
 }
 
 // Whether the image of the box (centre c, half extents h) under the recipe
-// words w can meet the cull box.
+// words w can meet the cull box and, for masks with an occupancy table, can
+// sample an occupied cell: the image's voxel indices (the nearest-neighbour
+// words carry the +0.5, so a sample's index is the floor of its coordinate)
+// lie in [floor(uc - r), floor(uc + r)] per axis; clipped to the source and
+// taken to cells, the table's inclusion-exclusion count over that cell box is
+// the number of occupied cells it holds.  None occupied: every sample reads an
+// off bit and adds nothing to a or c.
 template <typename P>
 __device__ __forceinline__ bool box_reaches(P w, const float c[3], const float h[3], const KArgs &a) {
     bool ok = true;
+    int32_t lo[3], hi[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const float uc = fmaf(w[4 * d + 2], c[2], fmaf(w[4 * d + 1], c[1], fmaf(w[4 * d], c[0], w[4 * d + 3])));
         const float r = fmaf(fabsf(w[4 * d + 2]), h[2], fmaf(fabsf(w[4 * d + 1]), h[1], fabsf(w[4 * d]) * h[0])) +
                         kCullMargin;
         ok = ok && uc + r >= a.cull_lo[d] && uc - r <= a.cull_hi[d];
+        lo[d] = (int32_t)floorf(fmaxf(uc - r, 0.0f));
+        hi[d] = (int32_t)floorf(fminf(uc + r, a.occ_hi[d]));
+    }
+    if (ok && a.occ) {
+        if (lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2]) return false;
+        const uint32_t x0 = (uint32_t)lo[0] >> kOccShift, x1 = ((uint32_t)hi[0] >> kOccShift) + 1u;
+        const uint32_t y0 = ((uint32_t)lo[1] >> kOccShift) * a.ocx, y1 = (((uint32_t)hi[1] >> kOccShift) + 1u) * a.ocx;
+        const uint32_t z0 = ((uint32_t)lo[2] >> kOccShift) * a.ocxy,
+                       z1 = (((uint32_t)hi[2] >> kOccShift) + 1u) * a.ocxy;
+        const uint32_t *S = a.occ;
+        const uint32_t n = S[z1 + y1 + x1] - S[z0 + y1 + x1] - S[z1 + y0 + x1] - S[z1 + y1 + x0] +
+                           S[z0 + y0 + x1] + S[z0 + y1 + x0] + S[z1 + y0 + x0] - S[z0 + y0 + x0];
+        ok = n != 0u;
     }
     return ok;
 }
@@ -924,11 +950,17 @@ __device__ __forceinline__ uint32_t list_begin(uint32_t total, uint32_t x) {
     return x * q + min(x, rem);
 }
 
+// work (or nullptr): adds the particle x voxel pairs of the live particles of
+// the items (evaluated) and of all their particles (covered), one atomic pair
+// per wave into one of kWorkSlots counter pairs (each on its own cache line,
+// so the waves' atomics do not queue on one address).
 template <int PT>
-__global__ __launch_bounds__(256) void k_cull_items(const KArgs a, uint32_t total, uint2 *items, uint32_t *counts) {
+__global__ __launch_bounds__(256) void k_cull_items(const KArgs a, uint32_t total, uint2 *items, uint32_t *counts,
+                                                    unsigned long long *work) {
     const uint32_t w = blockIdx.x * 256u + threadIdx.x;
     const uint32_t groups = (a.np + PT - 1) / PT;
     uint32_t live = 0u, x = 0u;
+    unsigned long long evaluated = 0ull, covered = 0ull;
     if (w < total) {
         const uint32_t bx = w / groups, by = w - bx * groups;
         const int tiles = a.tiles_x * a.tiles_y;
@@ -944,9 +976,22 @@ __global__ __launch_bounds__(256) void k_cull_items(const KArgs a, uint32_t tota
         for (uint32_t p = 0; p < npg; ++p)
             if (box_reaches(a.words + 12 * (size_t)(pbase + p), c, h, a)) live |= 1u << p;
         while (x < 7u && w >= list_begin(total, x + 1u)) ++x;
+        const unsigned long long vox =
+            (unsigned long long)(hi[0] - lo[0] + 1) * (unsigned long long)(hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+        evaluated = (unsigned long long)__popc(live) * vox;
+        covered = (unsigned long long)npg * vox;
+    }
+    const uint32_t lane = threadIdx.x % 64u;
+    if (work) {
+        evaluated = wave_sum(evaluated);
+        covered = wave_sum(covered);
+        if (lane == 0u) {
+            unsigned long long *slot = work + kWorkSlotWords * ((blockIdx.x * 4u + threadIdx.x / 64u) % kWorkSlots);
+            atomicAdd(slot, evaluated);
+            atomicAdd(slot + 1, covered);
+        }
     }
     // one atomic per wave when all its lanes fall in one list (the usual case)
-    const uint32_t lane = threadIdx.x % 64u;
     const uint32_t x0 = __shfl(x, 0);
     const bool one_list = __all(x == x0);
     const uint64_t m = __ballot(live != 0u);
@@ -1156,6 +1201,12 @@ KArgs make_args(const ScoreLaunch &L, int pt, int *nz_chunks) {
     a.tn2 = L.tn[2];
     a.p0 = L.p0;
     a.np = L.np;
+    // occupancy culling: masks' culled launches with a table
+    const bool occ = L.mode == kModeMask && L.cull_box && L.occ;
+    a.occ = occ ? L.occ : nullptr;
+    a.ocx = (uint32_t)((L.sn[0] + (1 << kOccShift) - 1) >> kOccShift) + 1u;
+    a.ocxy = a.ocx * ((uint32_t)((L.sn[1] + (1 << kOccShift) - 1) >> kOccShift) + 1u);
+    for (int d = 0; d < 3; ++d) a.occ_hi[d] = (float)(L.sn[d] - 1);
     a.tiles_x = (L.tn[0] + kTX - 1) / kTX;
     a.tiles_y = (L.tn[1] + kTY - 1) / kTY;
     const int zc = L.zchunk > 0 ? std::min(L.zchunk, kZChunkMax) : kZChunkMax;
@@ -1405,7 +1456,7 @@ hipError_t launch_mask_items_pt(const KArgs &a, uint32_t total, const ScoreLaunc
     hipError_t e = launch_fill_u64((unsigned long long *)L.item_counters, kItemCounterWords / 2, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cull_items<PT>, dim3((total + 255u) / 256u), dim3(256), 0, s, a, total, (uint2 *)L.items,
-                       counts);
+                       counts, probe ? nullptr : L.work);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (probe) {
         const int blocks = persistent_blocks(reinterpret_cast<const void *>(k_probe_mask_items<PT>));

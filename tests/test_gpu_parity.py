@@ -681,6 +681,32 @@ def test_work_items_beyond_one_grid_are_refused(smc):
     r.close()
 
 
+def test_profile_work_counts_the_culled_launches(smc):
+    """smc_profile_work: a registration's culled mask launches cover every
+    particle x voxel pair of the target grid once per launch (N + 1 particles
+    per iteration, and the final estimate's own score) and evaluate at most
+    those; the counters clear on reading; image contexts report 0."""
+    pair = synth.shell_pair(seed=3, side=48)
+    prm = config.default_params("dice", 256, 4, 15.0, 5.0, seed=9)
+    r = _reg(smc, pair, prm)
+    r.profile(True)
+    r.profile_read()
+    assert r.profile_work() == dict(evaluated=0, covered=0)
+    r.run()
+    n = r.profile_read()["score_launches"]
+    w = r.profile_work()
+    V = pair["tgt"].size
+    assert n == 4 and w["covered"] % V == 0 and w["covered"] // V == 257 * n + 1
+    assert 0 < w["evaluated"] <= w["covered"]
+    assert r.profile_work() == dict(evaluated=0, covered=0)
+    r.close()
+    sp = synth.speckle_pair(side=40, seed=5, trans=3.0)
+    r = _reg(smc, sp, config.default_params("ncc", 64, 2, 20.0, 3.0), src_fov=sp["src_fov"])
+    r.run()
+    assert r.profile_work() == dict(evaluated=0, covered=0)
+    r.close()
+
+
 def test_gather_probe_leaves_the_filter_alone(smc):
     """smc_gather_probe times its probe and the scoring launch on the current
     particle set without touching the filter: a registration probed before
