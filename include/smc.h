@@ -268,7 +268,7 @@ smc_status smc_profile_read(smc_ctx *ctx, double *score_ms, uint64_t *score_laun
  * evaluation; image contexts report 0).  Tile culling skips a particle for a
  * target tile when no sample of the tile's image can read an "on" source
  * voxel: the image's box misses the source mask's bounding box or covers only
- * unoccupied 4^3-voxel cells.  Returns, since the previous call (or
+ * unoccupied 2^3-voxel cells.  Returns, since the previous call (or
  * smc_init), the particle x voxel pairs those launches evaluated and the
  * pairs they covered (the skipped ones included), and clears both.  Syncs
  * the context's stream.  Outputs may be NULL. */

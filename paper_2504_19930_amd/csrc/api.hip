@@ -559,7 +559,7 @@ smc_status smc_init(smc_ctx **out, const smc_volume *src, const smc_volume *tgt,
                 c->box_lo[d] = hb[d];
                 c->box_hi[d] = hb[3 + d];
             }
-        // occupancy of 4^3-voxel cells for the culled launches, when its table
+        // occupancy of 2^3-voxel cells for the culled launches, when its table
         // is modest (flat volumes would make its zero borders large)
         if ((st = c->alloc(&c->work, kWorkSlots * kWorkSlotWords)) != SMC_OK) return bail(st);
         if (launch_fill_u64(c->work, kWorkSlots * kWorkSlotWords, c->stream) != hipSuccess)

@@ -154,7 +154,7 @@ hipError_t launch_pack_mask_bits(const uint8_t *prep, const int32_t n[3], uint32
 // Occupancy of the prepared source mask's "on" bits over cells of
 // 2^kOccShift voxels a side, as a summed-area table with a zero first row,
 // column and slice: words of the table, and the building launches.
-constexpr int kOccShift = 2;
+constexpr int kOccShift = 1;
 constexpr uint64_t kOccMaxWords = 16ull << 20;  // 64 MB
 constexpr uint32_t kWorkSlots = 64, kWorkSlotWords = 16;
 uint64_t mask_occ_words(const int32_t n[3]);

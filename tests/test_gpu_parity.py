@@ -159,6 +159,29 @@ def test_full_filter_shell64_matches_oracle(smc, orc):
     _compare_runs(smc, orc, pair, config.workload_params("shell64"))
 
 
+def test_full_filter_sparse_mask_matches_oracle(smc, orc):
+    """Masks whose occupied 2^3 cells are few and scattered (isolated voxels,
+    partial cells on the volume's far faces, a non-multiple-of-4 shape), where
+    the occupied-cell cull skips most of the bounding box: the whole filter
+    matches the oracle, and the culled launches evaluated fewer pairs than
+    they covered."""
+    rng = np.random.default_rng(21)
+    shape = (29, 41, 37)  # z, y, x
+    src = np.zeros(shape, np.uint8)
+    idx = rng.choice(src.size, 60, replace=False)
+    src.flat[idx] = 1
+    src[-1, -1, -1] = src[0, 0, 0] = src[-1, 0, -1] = 1  # corners of the grid
+    src[10:14, 20:26, 15:19] = 1                         # one solid block
+    tgt = np.roll(src, (1, -2, 1), axis=(0, 1, 2))
+    prm = config.default_params("dice", 192, 4, 12.0, 3.0, seed=6)
+    r, _ = _compare_runs(smc, orc, dict(src=src, tgt=tgt), prm)
+    r.profile_work()
+    r.reset(6)
+    r.run()
+    w = r.profile_work()
+    assert 0 < w["evaluated"] < w["covered"]
+
+
 def test_full_filter_image_ncc_and_ssd(smc, orc):
     pair = synth.speckle_pair(side=40, seed=9, trans=3.0)
     for score in ("ncc", "ssd"):
