@@ -100,10 +100,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const uint8_t *p, ui
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(p), (short)0, (int)bytes, kBufferWord3);
 }
 
-// Staged trilinear kernel.  LDS layout: 16 zero bytes (samples outside the
-// source read them, with fractions 0), then the box: rows of P bytes, slices
-// of Pz bytes, one more row and slice for the +1 taps.  The box of frame f + 1
-// is loaded into registers while frame f is computed.
 // Write one frame's output tile, assembled in LDS as ZC slices x kWY rows x
 // kWX bytes, with 16-byte stores: thread t takes half t % 2 of row t / 2
 // (rows past the target, and the tail of a row past its end, are skipped; a
@@ -131,6 +127,10 @@ __device__ __forceinline__ void store_tile(const uint8_t *tile, const WArgs &a, 
     }
 }
 
+// Staged trilinear kernel.  LDS layout: 16 zero bytes (samples outside the
+// source read them, with fractions 0), then the box: rows of P bytes, slices
+// of Pz bytes, one more row and slice for the +1 taps.  The box of frame f + 1
+// is loaded into registers while frame f is computed.
 template <int ZC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ZC == 16 ? 3 : 4)))
 void k_warp_trilinear_lds(const WArgs a) {
