@@ -221,8 +221,8 @@ smc_status smc_set_frames(smc_ctx *ctx, uint32_t n_extra, const smc_volume *src_
  * over a target column, 4, 8 or 16.  tile_depth: target
  * slices per tile, 1 .. 256 (a tile is 32 x 8 x tile_depth voxels; shallower
  * tiles cull more exactly -- a tile whose image cannot reach the source, or
- * in the filter the source mask's bounding box, is skipped -- at the cost of
- * more partial sums).  A negative value keeps the current setting.  Defaults
+ * in the filter the source mask's bounding box or any occupied 2^3-voxel
+ * cell of the source mask, is skipped -- at the cost of more partial sums).  A negative value keeps the current setting.  Defaults
  * come from measurements on MI355X: 4 particles per group; tile depth 16 for
  * masks and 256 for images.  A packed layout addresses its source
  * with 32-bit offsets: SMC_EINVAL if the packed source reaches 4 GiB or one
