@@ -34,6 +34,7 @@ static_assert(kWX == 16, "a wave's four quarters are 4 x 4 squares side by side 
 constexpr int kWaves = kThreads / 64;
 constexpr int kZChunkMax = 256;  // keeps every per-thread 32-bit sum below 2^32
 constexpr int kSlab = 32;        // target slices staged in LDS at a time
+constexpr uint32_t kItemChunk = 4;  // items a persistent workgroup takes at a time
 
 struct KArgs {
     const uint8_t *src, *src_ok, *tgt, *tgt_fov;
@@ -272,8 +273,13 @@ __device__ __forceinline__ uint32_t mad_u24v(uint32_t a, uint32_t b, uint32_t c)
 // bitmap puts the rows of a slice 4 ceil(nx / 32) bytes apart, so the rotated
 // footprint of a wave's samples spans a few cache lines instead of one or two
 // per source row and slice as with a byte per voxel.
+// staged (or nullptr): the key of the tile whose target slab the LDS holds,
+// kept by a persistent workgroup across its items; an item whose tile has
+// that key (tile_key: unique per tile among the workgroup's items) and fits
+// one slab reuses the slab instead of staging it again.
 template <int PT, bool AC = false, bool GIVEN = false>
-__device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t by, uint32_t live_in = 0u) {
+__device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t by, uint32_t live_in = 0u,
+                                          uint32_t *staged = nullptr, uint32_t tile_key = 0u) {
     const Tile t = tile_of<PT>(a, bx, by);
     // GIVEN: the cull pre-pass already tested this item (live_in != 0)
     const uint32_t live = GIVEN ? live_in : live_mask<PT>(a, t, bx);
@@ -306,11 +312,17 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
         __shared__ uint32_t tslab[kSlab * kThreads / 4];
         const uint8_t *tslab8 = (const uint8_t *)tslab;
         const uint32_t col = (uint32_t)(t.j - t.y0) * kTX + (uint32_t)(t.i - t.x0);
+        const bool one_slab = t.k1 - t.k0 <= kSlab;
         for (int kb = t.k0; kb < t.k1; kb += kSlab) {
             const int ke = min(kb + kSlab, t.k1);
-            __syncthreads();  // every thread is done with the previous slab
-            stage_target(a, t, kb, ke, rs_t, rs_t, false, tslab, tslab);
-            __syncthreads();
+            if (!(staged && one_slab && *staged == tile_key)) {
+                __syncthreads();  // every thread is done with the previous slab
+                stage_target(a, t, kb, ke, rs_t, rs_t, false, tslab, tslab);
+                __syncthreads();
+                if (staged) *staged = one_slab ? tile_key : 0xFFFFFFFFu;
+            } else {
+                __syncthreads();  // the previous item's reduction slots are read
+            }
             if (!t.ok) continue;
             for (int k = kb; k < ke; ++k) {
                 const uint32_t tb = tslab8[(uint32_t)(k - kb) * kThreads + col];
@@ -1016,17 +1028,23 @@ __global__ __launch_bounds__(kThreads) void k_score_mask_items(const KArgs a, co
                                                                uint32_t total) {
     __shared__ uint32_t next_item;
     const uint32_t groups = (a.np + PT - 1) / PT;
+    uint32_t staged = 0xFFFFFFFFu;  // tile whose target slab the LDS holds (none yet)
     for (uint32_t s = 0; s < 8; ++s) {
         const uint32_t x = (blockIdx.x + s) % 8u;
         const uint32_t begin = list_begin(total, x), n_items = counts[x * kListStride];
         for (;;) {
-            if (threadIdx.x == 0) next_item = atomicAdd(take + x * kListStride, 1u);
+            // kItemChunk consecutive items at a time: the pre-pass appends a
+            // wave's items (mostly of one tile) together
+            if (threadIdx.x == 0) next_item = atomicAdd(take + x * kListStride, kItemChunk);
             __syncthreads();
-            const uint32_t r = next_item;
-            if (r >= n_items) break;
-            const uint2 it = items[begin + r];
-            const uint32_t bx = it.x / groups, by = it.x - bx * groups;
-            mask_body<PT, true, true>(a, bx, by, it.y);
+            const uint32_t r0 = next_item;
+            if (r0 >= n_items) break;
+            const uint32_t r1 = min(r0 + kItemChunk, n_items);
+            for (uint32_t r = r0; r < r1; ++r) {
+                const uint2 it = items[begin + r];
+                const uint32_t bx = it.x / groups, by = it.x - bx * groups;
+                mask_body<PT, true, true>(a, bx, by, it.y, &staged, bx);
+            }
             __syncthreads();  // next_item is read by all before thread 0 takes the next
         }
         __syncthreads();  // the same before the next list's first take
@@ -1160,21 +1178,26 @@ __global__ __launch_bounds__(kThreads) void k_batch_mask_items(const BatchArgs b
                                                                const uint32_t *counts) {
     const auto *pairs = as_const(b.pairs);
     __shared__ uint32_t next_item;
+    // key of the tile whose target slab the LDS holds: the batch-wide index of
+    // the tile's first item (none yet)
+    uint32_t staged = 0xFFFFFFFFu;
     for (uint32_t s = 0; s < 8; ++s) {
         const uint32_t x = (blockIdx.x + s) % 8;
         const uint32_t begin = b.list_off[x], n_items = counts[x * kListStride];
         for (;;) {
-            if (threadIdx.x == 0) next_item = atomicAdd(b.counters + x, 1u);
+            if (threadIdx.x == 0) next_item = atomicAdd(b.counters + x, kItemChunk);
             __syncthreads();
-            const uint32_t r = next_item;
-            if (r >= n_items) break;
-            const uint2 it = live[begin + r];
-            const uint32_t d = pair_of(b.offs, b.n_pairs, it.x);
-            const KArgs a = pairs[d];
-            const uint32_t local = it.x - b.offs[d];
-            const uint32_t ng = (a.np + PT - 1) / PT;
-            const uint32_t bx = local / ng, by = local - bx * ng;
-            mask_body<PT, true, true>(a, bx, by, it.y);
+            const uint32_t r0 = next_item;
+            if (r0 >= n_items) break;
+            for (uint32_t r = r0; r < min(r0 + kItemChunk, n_items); ++r) {
+                const uint2 it = live[begin + r];
+                const uint32_t d = pair_of(b.offs, b.n_pairs, it.x);
+                const KArgs a = pairs[d];
+                const uint32_t local = it.x - b.offs[d];
+                const uint32_t ng = (a.np + PT - 1) / PT;
+                const uint32_t bx = local / ng, by = local - bx * ng;
+                mask_body<PT, true, true>(a, bx, by, it.y, &staged, it.x - by);
+            }
             __syncthreads();  // next_item is read by all before thread 0 takes the next
         }
         __syncthreads();  // the same before the next list's first take
@@ -1618,13 +1641,15 @@ __global__ __launch_bounds__(kThreads) void k_probe_mask_items(const KArgs a, co
         const uint32_t x = (blockIdx.x + s) % 8u;
         const uint32_t begin = list_begin(total, x), n_items = counts[x * kListStride];
         for (;;) {
-            if (threadIdx.x == 0) next_item = atomicAdd(take + x * kListStride, 1u);
+            if (threadIdx.x == 0) next_item = atomicAdd(take + x * kListStride, kItemChunk);
             __syncthreads();
-            const uint32_t r = next_item;
-            if (r >= n_items) break;
-            const uint2 it = items[begin + r];
-            const uint32_t bx = it.x / groups, by = it.x - bx * groups;
-            chk ^= probe_mask_body<PT, true, true>(a, bx, by, it.y);
+            const uint32_t r0 = next_item;
+            if (r0 >= n_items) break;
+            for (uint32_t r = r0; r < min(r0 + kItemChunk, n_items); ++r) {
+                const uint2 it = items[begin + r];
+                const uint32_t bx = it.x / groups, by = it.x - bx * groups;
+                chk ^= probe_mask_body<PT, true, true>(a, bx, by, it.y);
+            }
             __syncthreads();
         }
         __syncthreads();
