@@ -14,6 +14,9 @@ namespace {
 
 constexpr int kFT = 1024;  // filter workgroup
 constexpr int kFW = kFT / 64;
+// Particles whose resampling CDF the filter workgroup keeps in LDS (32 KB);
+// larger sets search the CDF in global memory.
+constexpr uint32_t kCdfLds = 4096;
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -136,8 +139,12 @@ __device__ __forceinline__ void filter_body(const FilterState &f, const uint32_t
     __shared__ double bcast[12];
     __shared__ uint32_t ref_idx[kFW];
     __shared__ unsigned long long scan[kFT];
+    __shared__ unsigned long long cdf_lds[kCdfLds];
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const uint32_t n = f.n;
+    // the binary searches of the resampling step read this CDF: each search is
+    // a chain of dependent loads, far shorter from LDS than from L2
+    unsigned long long *const cdf = n <= kCdfLds ? cdf_lds : f.cdf;
 
     // update: log-weights of the scores, and their maximum; a set drawn from
     // the proposal carries the importance correction in its first update
@@ -259,7 +266,7 @@ __device__ __forceinline__ void filter_body(const FilterState &f, const uint32_t
         unsigned long long run = scan[tid] - local;
         for (uint32_t i = b0; i < b1; ++i) {
             run += (unsigned long long)floor(f.w[i] * 0x1p48);
-            f.cdf[i] = run;
+            cdf[i] = run;
         }
         const unsigned long long Q = scan[kFT - 1];
         __syncthreads();
@@ -278,7 +285,7 @@ __device__ __forceinline__ void filter_body(const FilterState &f, const uint32_t
             uint32_t lo = 0, hi = n - 1;
             while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
-                if (pointer_passed(f.cdf[mid], scale, rhs)) hi = mid;
+                if (pointer_passed(cdf[mid], scale, rhs)) hi = mid;
                 else lo = mid + 1;
             }
             f.anc[j] = (int32_t)lo;
