@@ -358,6 +358,30 @@ def test_warp_apply_kernels_bit_exact(smc, orc, interp, case):
         assert not got.any()
 
 
+@pytest.mark.parametrize("interp", ["nearest", "trilinear"])
+def test_warp_apply_degenerate_sizes(smc, orc, interp):
+    """Tiny and flat grids on every warp kernel: one-voxel outputs, a source of
+    exactly 16 bytes (the smallest the staged kernel takes) and one of 12
+    (direct), single-slice and single-row volumes, and a single frame."""
+    import torch
+    rng = np.random.default_rng(41)
+    cases = [((4, 2, 2), (1, 1, 1)), ((4, 2, 2), (5, 3, 2)), ((4, 3, 1), (6, 2, 3)), ((8, 1, 5), (3, 4, 1)),
+             ((32, 1, 1), (40, 1, 1)), ((12, 4, 3), (9, 9, 9))]
+    for sshape, tshape in cases:
+        for M in (np.hstack([np.eye(3), [[0.25], [0.0], [-0.5]]]),
+                  _rot_matrix((0.2, 0.7, -0.4), 9.0, np.asarray(sshape) / 2.0, (0.3, -0.2, 0.1))):
+            frames = rng.integers(0, 256, (3, sshape[2], sshape[1], sshape[0])).astype(np.uint8)
+            src = dev(frames)
+            for F in (1, 3):
+                out = torch.full((F, tshape[2], tshape[1], tshape[0]), 7, dtype=torch.uint8, device="cuda")
+                smc.warp_apply(smc.volume(src[0]), M, interp, out, n_frames=F, src_frame_stride=frames[0].size,
+                               dst_frame_stride=int(np.prod(tshape)))
+                got = out.cpu().numpy()
+                for f in range(F):
+                    want = orc.warp_apply(orc.Volume(frames[f]), M, interp == "trilinear", tshape)
+                    assert np.array_equal(got[f], want), (sshape, tshape, F, f)
+
+
 # ------------------------------------------------------------------ full-size workloads
 
 def test_speckle160_full_size_sampled(smc, orc):
