@@ -148,7 +148,9 @@ def mask_roofline(launch_ms, launches, work, N, V, probe):
     evaluated, covered = frac_eval * grid, grid
     r = roofline("k_score_mask (warp-and-score, nearest, Dice counts)", OPS_PER_EVAL_MASK, evaluated, launch_ms,
                  launches, GATHER_BYTES_MASK, PMC_MASK, probe)
+    frac_int = work.get("interior", 0) / work["evaluated"] if work["evaluated"] else 0.0
     r.update({"evals_per_launch_covered": covered, "evaluated_fraction": frac_eval,
+              "interior_fraction_of_evaluated": frac_int,
               "evals_note": "evals_per_launch = particle x voxel pairs evaluated per launch (the culled ones "
                             "excluded): the fraction the cull pre-pass counted over the timed registrations times "
                             "the launch's (N + 1) x V pairs"})

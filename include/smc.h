@@ -269,10 +269,12 @@ smc_status smc_profile_read(smc_ctx *ctx, double *score_ms, uint64_t *score_laun
  * target tile when no sample of the tile's image can read an "on" source
  * voxel: the image's box misses the source mask's bounding box or covers only
  * unoccupied 2^3-voxel cells.  Returns, since the previous call (or
- * smc_init), the particle x voxel pairs those launches evaluated and the
- * pairs they covered (the skipped ones included), and clears both.  Syncs
- * the context's stream.  Outputs may be NULL. */
-smc_status smc_profile_work(smc_ctx *ctx, uint64_t *evaluated, uint64_t *covered);
+ * smc_init), the particle x voxel pairs those launches evaluated, the pairs
+ * they covered (the skipped ones included) and, of the evaluated ones, those
+ * of tiles whose every sample the cull bound places inside the source (scored
+ * without the per-sample inside test), and clears all three.  Syncs the
+ * context's stream.  Outputs may be NULL. */
+smc_status smc_profile_work(smc_ctx *ctx, uint64_t *evaluated, uint64_t *covered, uint64_t *interior);
 
 /* Free everything the context owns (after syncing its stream).  NULL is a no-op. */
 void smc_destroy(smc_ctx *ctx);

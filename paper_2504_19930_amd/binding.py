@@ -83,7 +83,7 @@ def lib():
             "warp_apply": [P(SmcVolume), vp, i32, vp, i32, i32, i32, dp, dp, dp, u32, i64, i64, vp],
             "smc_profile": [vp, i32],
             "smc_profile_read": [vp, vp, vp, vp, vp],
-            "smc_profile_work": [vp, vp, vp],
+            "smc_profile_work": [vp, vp, vp, vp],
             "smc_set_tuning": [vp, i32, i32, i32],
             "smc_set_frames": [vp, u32, vp, vp],
             "smc_score_particles": [vp, vp, u32, vp],
@@ -275,9 +275,10 @@ def smc_profile(ctx, enable: bool):
 
 
 def smc_profile_work(ctx) -> dict:
-    ev, cov = C.c_uint64(), C.c_uint64()
-    _check(lib().smc_profile_work(ctx, C.cast(C.byref(ev), C.c_void_p), C.cast(C.byref(cov), C.c_void_p)))
-    return dict(evaluated=ev.value, covered=cov.value)
+    ev, cov, inr = C.c_uint64(), C.c_uint64(), C.c_uint64()
+    _check(lib().smc_profile_work(ctx, C.cast(C.byref(ev), C.c_void_p), C.cast(C.byref(cov), C.c_void_p),
+                                  C.cast(C.byref(inr), C.c_void_p)))
+    return dict(evaluated=ev.value, covered=cov.value, interior=inr.value)
 
 
 def smc_profile_read(ctx) -> dict:
@@ -446,8 +447,8 @@ class Registration:
         return smc_profile_read(self.ctx)
 
     def profile_work(self):
-        """Particle x voxel pairs the culled mask launches evaluated and
-        covered since the previous call."""
+        """Particle x voxel pairs the culled mask launches evaluated, covered
+        and evaluated on interior tiles since the previous call."""
         return smc_profile_work(self.ctx)
 
     def gather_probe(self, reps=1):

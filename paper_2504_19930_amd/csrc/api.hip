@@ -1230,7 +1230,7 @@ smc_status smc_profile_read(smc_ctx *c, double *score_ms, uint64_t *score_n, dou
     return SMC_OK;
 }
 
-smc_status smc_profile_work(smc_ctx *c, uint64_t *evaluated, uint64_t *covered) {
+smc_status smc_profile_work(smc_ctx *c, uint64_t *evaluated, uint64_t *covered, uint64_t *interior) {
     if (!c) return fail(SMC_EINVAL, "ctx is NULL");
     smc_status st;
     if ((st = set_device(c)) != SMC_OK) return st;
@@ -1241,13 +1241,15 @@ smc_status smc_profile_work(smc_ctx *c, uint64_t *evaluated, uint64_t *covered) 
         HIP_TRY(launch_fill_u64(c->work, kWorkSlots * kWorkSlotWords, c->stream));
     }
     HIP_TRY(hipStreamSynchronize(c->stream));
-    uint64_t ev = 0, cov = 0;
+    uint64_t ev = 0, cov = 0, in = 0;
     for (uint32_t q = 0; q < kWorkSlots; ++q) {
         ev += w[q * kWorkSlotWords];
         cov += w[q * kWorkSlotWords + 1];
+        in += w[q * kWorkSlotWords + 2];
     }
     if (evaluated) *evaluated = ev;
     if (covered) *covered = cov;
+    if (interior) *interior = in;
     return SMC_OK;
 }
 

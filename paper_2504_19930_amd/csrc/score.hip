@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -35,6 +36,10 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kZChunkMax = 256;  // keeps every per-thread 32-bit sum below 2^32
 constexpr int kSlab = 32;        // target slices staged in LDS at a time
 constexpr uint32_t kItemChunk = 4;  // items a persistent workgroup takes at a time
+// An item's second word: bit p for each live particle p (PT <= 16), and bit
+// kInteriorBit when every live particle's image of the tile lies inside the
+// source, so the scoring kernel can skip the per-sample inside test.
+constexpr uint32_t kInteriorBit = 16;
 
 struct KArgs {
     const uint8_t *src, *src_ok, *tgt, *tgt_fov;
@@ -205,6 +210,22 @@ __device__ __forceinline__ bool box_reaches(P w, const float c[3], const float h
     return ok;
 }
 
+// Whether every sample of the box's image under the nearest-neighbour words w
+// lies inside the source (0 <= u < n per axis), by the same bound.
+template <typename P>
+__device__ __forceinline__ bool box_inside(P w, const float c[3], const float h[3], const KArgs &a) {
+    const float n[3] = {(float)a.sn0, (float)a.sn1, (float)a.sn2};
+    bool in = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float uc = fmaf(w[4 * d + 2], c[2], fmaf(w[4 * d + 1], c[1], fmaf(w[4 * d], c[0], w[4 * d + 3])));
+        const float r = fmaf(fabsf(w[4 * d + 2]), h[2], fmaf(fabsf(w[4 * d + 1]), h[1], fabsf(w[4 * d]) * h[0])) +
+                        kCullMargin;
+        in = in && uc - r >= 0.0f && uc + r < n[d];
+    }
+    return in;
+}
+
 template <int PT>
 __device__ __forceinline__ uint32_t live_mask(const KArgs &a, const Tile &t, uint32_t bx) {
     const int tiles = a.tiles_x * a.tiles_y;
@@ -286,6 +307,19 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
     if (live == 0u) return;  // nothing of this tile can reach the source region
     float mx[PT], my[PT], mz[PT], ax[PT], ay[PT], az[PT];
     column_terms<PT>(a, t, mx, my, mz, ax, ay, az);
+    // interior (bit kInteriorBit of a pre-pass item): every sample of the
+    // live particles lies inside the source, so the inside test is dropped;
+    // the other particle slots are pointed at slice n_z, whose offset
+    // (n_z times the slice stride) is the bitmap's end, where loads read zero
+    const bool interior = GIVEN && AC && ((live_in >> kInteriorBit) & 1u) != 0u;
+    if (interior) {
+#pragma unroll
+        for (int p = 0; p < PT; ++p)
+            if (!((live >> p) & 1u)) {
+                ax[p] = ay[p] = az[p] = mx[p] = my[p] = 0.0f;
+                mz[p] = (float)a.sn2;
+            }
+    }
     if constexpr (PT > 4) {
         // the per-particle slopes are uniform; with many particles they would
         // crowd the scalar registers out (and be spilled to vector lanes)
@@ -324,6 +358,8 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
                 __syncthreads();  // the previous item's reduction slots are read
             }
             if (!t.ok) continue;
+            const auto slices = [&](auto interior_tag) {
+            constexpr bool INTERIOR = decltype(interior_tag)::value;
             for (int k = kb; k < ke; ++k) {
                 const uint32_t tb = tslab8[(uint32_t)(k - kb) * kThreads + col];
                 const uint32_t keep = (tb & 1u) ? 3u : 0u;
@@ -339,8 +375,6 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
                     const float ux = fmaf(ax[p], fk, mx[p]);
                     const float uy = fmaf(ay[p], fk, my[p]);
                     const float uz = fmaf(az[p], fk, mz[p]);
-                    const bool in = ((live >> p) & 1u) & (__float_as_uint(ux) < nxb) & (__float_as_uint(uy) < nyb) &
-                                    (__float_as_uint(uz) < nzb);
                     // 24-bit multiply-adds: exact inside (offsets below 2^32);
                     // outside samples (and particles culled for this tile) load
                     // from the buffer's end: zero, no cache lines touched, so they
@@ -353,7 +387,11 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
                     } else {
                         off[p] = mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, floor_u32(ux)));
                     }
-                    off[p] = in ? off[p] : nbytes;
+                    if constexpr (!INTERIOR) {
+                        const bool in = ((live >> p) & 1u) & (__float_as_uint(ux) < nxb) &
+                                        (__float_as_uint(uy) < nyb) & (__float_as_uint(uz) < nzb);
+                        off[p] = in ? off[p] : nbytes;
+                    }
                 }
                 uint32_t val[PT];
 #pragma unroll
@@ -374,6 +412,9 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
                     }
                 }
             }
+            };
+            if (interior) slices(std::true_type{});
+            else slices(std::false_type{});
         }
     }
     __shared__ unsigned long long red[kWaves][PT][4];
@@ -954,7 +995,9 @@ void k_score_image(const KArgs a) {
 // sequence, the part the XCD-aware grid gives XCD x -- and a persistent grid
 // takes items from its XCD's list through an atomic counter, then helps the
 // other lists.  Sums are integer additions, so the result does not depend on
-// which workgroup takes which item.
+// which workgroup takes which item.  An item whose live particles all map the
+// tile inside the source (by the cull's bound) is marked interior, and its
+// samples skip the inside test: three compares and a select per sample.
 constexpr uint32_t kListStride = 32;  // counter words 128 bytes apart
 
 __device__ __forceinline__ uint32_t list_begin(uint32_t total, uint32_t x) {
@@ -963,16 +1006,18 @@ __device__ __forceinline__ uint32_t list_begin(uint32_t total, uint32_t x) {
 }
 
 // work (or nullptr): adds the particle x voxel pairs of the live particles of
-// the items (evaluated) and of all their particles (covered), one atomic pair
-// per wave into one of kWorkSlots counter pairs (each on its own cache line,
-// so the waves' atomics do not queue on one address).
+// the items (evaluated), of all their particles (covered) and of the live
+// particles of interior items (interior), one atomic per count and wave into
+// one of kWorkSlots counter triples (each on its own cache line, so the waves'
+// atomics do not queue on one address).
 template <int PT>
 __global__ __launch_bounds__(256) void k_cull_items(const KArgs a, uint32_t total, uint2 *items, uint32_t *counts,
                                                     unsigned long long *work) {
+    static_assert(PT <= (int)kInteriorBit, "particle bits below the interior bit");
     const uint32_t w = blockIdx.x * 256u + threadIdx.x;
     const uint32_t groups = (a.np + PT - 1) / PT;
     uint32_t live = 0u, x = 0u;
-    unsigned long long evaluated = 0ull, covered = 0ull;
+    unsigned long long evaluated = 0ull, covered = 0ull, interior = 0ull;
     if (w < total) {
         const uint32_t bx = w / groups, by = w - bx * groups;
         const int tiles = a.tiles_x * a.tiles_y;
@@ -985,22 +1030,32 @@ __global__ __launch_bounds__(256) void k_cull_items(const KArgs a, uint32_t tota
         float c[3], h[3];
         box_centre(lo, hi, c, h);
         const uint32_t pbase = a.p0 + by * PT, npg = min((uint32_t)PT, a.p0 + a.np - pbase);
+        bool inside = true;
         for (uint32_t p = 0; p < npg; ++p)
-            if (box_reaches(a.words + 12 * (size_t)(pbase + p), c, h, a)) live |= 1u << p;
+            if (box_reaches(a.words + 12 * (size_t)(pbase + p), c, h, a)) {
+                live |= 1u << p;
+                inside = inside && box_inside(a.words + 12 * (size_t)(pbase + p), c, h, a);
+            }
         while (x < 7u && w >= list_begin(total, x + 1u)) ++x;
         const unsigned long long vox =
             (unsigned long long)(hi[0] - lo[0] + 1) * (unsigned long long)(hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
         evaluated = (unsigned long long)__popc(live) * vox;
         covered = (unsigned long long)npg * vox;
+        if (live && inside) {
+            live |= 1u << kInteriorBit;
+            interior = evaluated;
+        }
     }
     const uint32_t lane = threadIdx.x % 64u;
     if (work) {
         evaluated = wave_sum(evaluated);
         covered = wave_sum(covered);
+        interior = wave_sum(interior);
         if (lane == 0u) {
             unsigned long long *slot = work + kWorkSlotWords * ((blockIdx.x * 4u + threadIdx.x / 64u) % kWorkSlots);
             atomicAdd(slot, evaluated);
             atomicAdd(slot + 1, covered);
+            atomicAdd(slot + 2, interior);
         }
     }
     // one atomic per wave when all its lanes fall in one list (the usual case)
@@ -1121,11 +1176,12 @@ void k_batch_score(const BatchArgs b) {
 
 // Mask classes: the live items of an iteration.  One thread per entry of the
 // class's XCD lists tests its (tile, particle group) item against its pair's
-// source mask box and appends live items, with their particle masks, to the
-// same list's part of `live` (one atomic per wave where all its lanes are in
-// one list); pairs past their last iteration add nothing.
+// source mask box and appends live items, with their particle masks and
+// interior bits, to the same list's part of `live` (one atomic per wave where
+// all its lanes are in one list); pairs past their last iteration add nothing.
 template <int PT>
 __global__ __launch_bounds__(256) void k_batch_cull(const BatchArgs b, uint2 *live, uint32_t *counts) {
+    static_assert(PT <= (int)kInteriorBit, "particle bits below the interior bit");
     const uint32_t e = blockIdx.x * 256u + threadIdx.x;
     const uint32_t total = b.list_off[8];
     uint32_t lm = 0u, x = 0u, g = 0u;
@@ -1148,8 +1204,13 @@ __global__ __launch_bounds__(256) void k_batch_cull(const BatchArgs b, uint2 *li
             float c[3], h[3];
             box_centre(lo, hi, c, h);
             const uint32_t pbase = a.p0 + by * PT, npg = min((uint32_t)PT, a.p0 + a.np - pbase);
+            bool inside = true;
             for (uint32_t p = 0; p < npg; ++p)
-                if (box_reaches(a.words + 12 * (size_t)(pbase + p), c, h, a)) lm |= 1u << p;
+                if (box_reaches(a.words + 12 * (size_t)(pbase + p), c, h, a)) {
+                    lm |= 1u << p;
+                    inside = inside && box_inside(a.words + 12 * (size_t)(pbase + p), c, h, a);
+                }
+            if (lm && inside) lm |= 1u << kInteriorBit;
         }
     }
     const uint32_t lane = threadIdx.x % 64u;
@@ -1550,25 +1611,42 @@ __device__ __forceinline__ uint32_t probe_mask_body(const KArgs &a, uint32_t bx,
         kBufferWord3);
     const uint32_t nxb = __float_as_uint((float)a.sn0), nyb = __float_as_uint((float)a.sn1),
                    nzb = __float_as_uint((float)a.sn2);
-    for (int k = t.k0; k < t.k1; ++k) {
-        const float fk = (float)k;
-        uint32_t off[PT];
-#pragma unroll
-        for (int p = 0; p < PT; ++p) {
-            const float ux = fmaf(ax[p], fk, mx[p]);
-            const float uy = fmaf(ay[p], fk, my[p]);
-            const float uz = fmaf(az[p], fk, mz[p]);
-            const bool in = ((live >> p) & 1u) & (__float_as_uint(ux) < nxb) & (__float_as_uint(uy) < nyb) &
-                            (__float_as_uint(uz) < nzb);
-            const uint32_t xo = AC ? (floor_u32(ux) >> 3) & ~3u : floor_u32(ux);
-            off[p] = mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, xo));
-            off[p] = in ? off[p] : (uint32_t)nbytes;
-        }
+    // the scoring kernel's interior items, as there
+    const bool interior = GIVEN && AC && ((live_in >> kInteriorBit) & 1u) != 0u;
+    if (interior) {
 #pragma unroll
         for (int p = 0; p < PT; ++p)
-            chk ^= AC ? __builtin_amdgcn_raw_buffer_load_b32(rs, off[p], 0, 0)
-                      : __builtin_amdgcn_raw_buffer_load_b8(rs, off[p], 0, 0);
+            if (!((live >> p) & 1u)) {
+                ax[p] = ay[p] = az[p] = mx[p] = my[p] = 0.0f;
+                mz[p] = (float)a.sn2;
+            }
     }
+    const auto slices = [&](auto interior_tag) {
+        constexpr bool INTERIOR = decltype(interior_tag)::value;
+        for (int k = t.k0; k < t.k1; ++k) {
+            const float fk = (float)k;
+            uint32_t off[PT];
+#pragma unroll
+            for (int p = 0; p < PT; ++p) {
+                const float ux = fmaf(ax[p], fk, mx[p]);
+                const float uy = fmaf(ay[p], fk, my[p]);
+                const float uz = fmaf(az[p], fk, mz[p]);
+                const uint32_t xo = AC ? (floor_u32(ux) >> 3) & ~3u : floor_u32(ux);
+                off[p] = mad_u24(floor_u32(uz), sn01, mad_u24(floor_u32(uy), sn0, xo));
+                if constexpr (!INTERIOR) {
+                    const bool in = ((live >> p) & 1u) & (__float_as_uint(ux) < nxb) &
+                                    (__float_as_uint(uy) < nyb) & (__float_as_uint(uz) < nzb);
+                    off[p] = in ? off[p] : (uint32_t)nbytes;
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < PT; ++p)
+                chk ^= AC ? __builtin_amdgcn_raw_buffer_load_b32(rs, off[p], 0, 0)
+                          : __builtin_amdgcn_raw_buffer_load_b8(rs, off[p], 0, 0);
+        }
+    };
+    if (interior) slices(std::true_type{});
+    else slices(std::false_type{});
     return chk;
 }
 

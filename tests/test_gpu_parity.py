@@ -429,10 +429,15 @@ def test_lv224_two_full_iterations_match_oracle(smc, orc):
     """The full-size mask volumes (224 x 208 x 176, Dice, default tuning)
     with N = 1024 particles: two whole iterations match the oracle's
     ancestors, log-weights, states and estimates (about 1.7e10 oracle
-    evaluations)."""
+    evaluations).  Both kinds of culled item ran: tiles whose every sample
+    the cull bound places inside the source (no per-sample inside test) and
+    tiles reaching past its faces."""
     seq = synth.lv_sequence(seed=3, frames=[0], speckle=False)
     prm = config.workload_params("lv224", n_iters=2, n_particles=1024)
-    _compare_runs(smc, orc, dict(src=seq["src"], tgt=seq["tgt"]), prm)
+    r, _ = _compare_runs(smc, orc, dict(src=seq["src"], tgt=seq["tgt"]), prm)
+    w = r.profile_work()
+    assert 0 < w["interior"] < w["evaluated"]
+    r.close()
 
 
 def test_lv224_full_size_sampled_and_warp_all_frames(smc, orc):
@@ -738,19 +743,19 @@ def test_profile_work_counts_the_culled_launches(smc):
     r = _reg(smc, pair, prm)
     r.profile(True)
     r.profile_read()
-    assert r.profile_work() == dict(evaluated=0, covered=0)
+    assert r.profile_work() == dict(evaluated=0, covered=0, interior=0)
     r.run()
     n = r.profile_read()["score_launches"]
     w = r.profile_work()
     V = pair["tgt"].size
     assert n == 4 and w["covered"] % V == 0 and w["covered"] // V == 257 * n + 1
-    assert 0 < w["evaluated"] <= w["covered"]
-    assert r.profile_work() == dict(evaluated=0, covered=0)
+    assert 0 < w["evaluated"] <= w["covered"] and 0 <= w["interior"] <= w["evaluated"]
+    assert r.profile_work() == dict(evaluated=0, covered=0, interior=0)
     r.close()
     sp = synth.speckle_pair(side=40, seed=5, trans=3.0)
     r = _reg(smc, sp, config.default_params("ncc", 64, 2, 20.0, 3.0), src_fov=sp["src_fov"])
     r.run()
-    assert r.profile_work() == dict(evaluated=0, covered=0)
+    assert r.profile_work() == dict(evaluated=0, covered=0, interior=0)
     r.close()
 
 
