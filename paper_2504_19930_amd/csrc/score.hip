@@ -40,6 +40,13 @@ constexpr uint32_t kItemChunk = 4;  // items a persistent workgroup takes at a t
 // kInteriorBit when every live particle's image of the tile lies inside the
 // source, so the scoring kernel can skip the per-sample inside test.
 constexpr uint32_t kInteriorBit = 16;
+// Bits 17..21 and 22..26: slices at the bottom and at the top of the item's
+// tile that no live particle's image can sample an occupied source cell
+// from (the pre-pass tests the tile's runs of kSpanSlices slices); the
+// scoring kernel skips them.  Zero: the whole tile.  Only tiles of at most
+// kSpanMaxDepth slices are trimmed.
+constexpr uint32_t kSpanLoBit = 17, kSpanHiBit = 22, kSpanMask = 31;
+constexpr int kSpanSlices = 4, kSpanMaxDepth = 32;
 
 struct KArgs {
     const uint8_t *src, *src_ok, *tgt, *tgt_fov;
@@ -347,6 +354,10 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
         const uint8_t *tslab8 = (const uint8_t *)tslab;
         const uint32_t col = (uint32_t)(t.j - t.y0) * kTX + (uint32_t)(t.i - t.x0);
         const bool one_slab = t.k1 - t.k0 <= kSlab;
+        // a pre-pass item's span: the slices of the tile some live particle
+        // can sample an occupied cell from (the whole tile otherwise)
+        const int kbeg = GIVEN ? t.k0 + (int)((live_in >> kSpanLoBit) & kSpanMask) : t.k0;
+        const int kend = GIVEN ? t.k1 - (int)((live_in >> kSpanHiBit) & kSpanMask) : t.k1;
         for (int kb = t.k0; kb < t.k1; kb += kSlab) {
             const int ke = min(kb + kSlab, t.k1);
             if (!(staged && one_slab && *staged == tile_key)) {
@@ -360,7 +371,7 @@ __device__ __forceinline__ void mask_body(const KArgs &a, uint32_t bx, uint32_t 
             if (!t.ok) continue;
             const auto slices = [&](auto interior_tag) {
             constexpr bool INTERIOR = decltype(interior_tag)::value;
-            for (int k = kb; k < ke; ++k) {
+            for (int k = max(kb, kbeg); k < min(ke, kend); ++k) {
                 const uint32_t tb = tslab8[(uint32_t)(k - kb) * kThreads + col];
                 const uint32_t keep = (tb & 1u) ? 3u : 0u;
                 const bool ton = (tb & 2u) != 0u;
@@ -997,7 +1008,9 @@ void k_score_image(const KArgs a) {
 // other lists.  Sums are integer additions, so the result does not depend on
 // which workgroup takes which item.  An item whose live particles all map the
 // tile inside the source (by the cull's bound) is marked interior, and its
-// samples skip the inside test: three compares and a select per sample.
+// samples skip the inside test: three compares and a select per sample.  The
+// pre-pass also tests the tile's bottom and top runs of kSpanSlices slices
+// with the same bound and trims those no live particle reaches.
 constexpr uint32_t kListStride = 32;  // counter words 128 bytes apart
 
 __device__ __forceinline__ uint32_t list_begin(uint32_t total, uint32_t x) {
@@ -1037,14 +1050,38 @@ __global__ __launch_bounds__(256) void k_cull_items(const KArgs a, uint32_t tota
                 inside = inside && box_inside(a.words + 12 * (size_t)(pbase + p), c, h, a);
             }
         while (x < 7u && w >= list_begin(total, x + 1u)) ++x;
-        const unsigned long long vox =
-            (unsigned long long)(hi[0] - lo[0] + 1) * (unsigned long long)(hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
-        evaluated = (unsigned long long)__popc(live) * vox;
-        covered = (unsigned long long)npg * vox;
+        const int depth = hi[2] - lo[2] + 1;
+        const unsigned long long area = (unsigned long long)(hi[0] - lo[0] + 1) * (unsigned long long)(hi[1] - lo[1] + 1);
+        covered = (unsigned long long)npg * area * depth;
+        // slices of the tile's bottom and top runs that no live particle reaches
+        int skip_lo = 0, skip_hi = 0;
+        if (live && depth > kSpanSlices && depth <= kSpanMaxDepth) {
+            const auto run_reaches = [&](int r0, int r1) {
+                const int rl[3] = {lo[0], lo[1], lo[2] + r0}, rh[3] = {hi[0], hi[1], lo[2] + r1};
+                float rc[3], rhh[3];
+                box_centre(rl, rh, rc, rhh);
+                bool any = false;
+                for (uint32_t p = 0; p < npg && !any; ++p)
+                    any = ((live >> p) & 1u) && box_reaches(a.words + 12 * (size_t)(pbase + p), rc, rhh, a);
+                return any;
+            };
+            while (skip_lo < depth && !run_reaches(skip_lo, min(skip_lo + kSpanSlices, depth) - 1))
+                skip_lo += kSpanSlices;
+            if (skip_lo >= depth) {
+                live = 0u;  // no run reaches an occupied cell: nothing of the tile can count
+            } else {
+                skip_lo = min(skip_lo, depth - 1);
+                int top = depth;  // runs from the top: [top - kSpanSlices, top)
+                while (top - kSpanSlices > skip_lo && !run_reaches(top - kSpanSlices, top - 1)) top -= kSpanSlices;
+                skip_hi = depth - top;
+            }
+        }
+        evaluated = (unsigned long long)__popc(live) * area * (unsigned long long)(depth - skip_lo - skip_hi);
         if (live && inside) {
             live |= 1u << kInteriorBit;
             interior = evaluated;
         }
+        if (live) live |= ((uint32_t)skip_lo << kSpanLoBit) | ((uint32_t)skip_hi << kSpanHiBit);
     }
     const uint32_t lane = threadIdx.x % 64u;
     if (work) {
@@ -1621,9 +1658,12 @@ __device__ __forceinline__ uint32_t probe_mask_body(const KArgs &a, uint32_t bx,
                 mz[p] = (float)a.sn2;
             }
     }
+    // the scoring kernel's item spans, as there
+    const int kbeg = GIVEN ? t.k0 + (int)((live_in >> kSpanLoBit) & kSpanMask) : t.k0;
+    const int kend = GIVEN ? t.k1 - (int)((live_in >> kSpanHiBit) & kSpanMask) : t.k1;
     const auto slices = [&](auto interior_tag) {
         constexpr bool INTERIOR = decltype(interior_tag)::value;
-        for (int k = t.k0; k < t.k1; ++k) {
+        for (int k = kbeg; k < kend; ++k) {
             const float fk = (float)k;
             uint32_t off[PT];
 #pragma unroll
