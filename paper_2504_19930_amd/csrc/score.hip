@@ -233,6 +233,36 @@ __device__ __forceinline__ bool box_inside(P w, const float c[3], const float h[
     return in;
 }
 
+// The slices of the bottom and top runs (kSpanSlices each) of the tile box
+// [lo, hi] that no live particle (bits of live; words w of particles 0 ..
+// npg - 1) can sample an occupied cell from, by box_reaches on each run's
+// box.  When no run is reached, live becomes 0.  Tiles deeper than
+// kSpanMaxDepth are left whole.
+template <typename P>
+__device__ __forceinline__ void trim_span(const KArgs &a, P w, uint32_t npg, const int lo[3], const int hi[3],
+                                          uint32_t &live, int &skip_lo, int &skip_hi) {
+    const int depth = hi[2] - lo[2] + 1;
+    skip_lo = skip_hi = 0;
+    if (!live || depth <= kSpanSlices || depth > kSpanMaxDepth) return;
+    const auto run_reaches = [&](int r0, int r1) {
+        const int rl[3] = {lo[0], lo[1], lo[2] + r0}, rh[3] = {hi[0], hi[1], lo[2] + r1};
+        float rc[3], rhh[3];
+        box_centre(rl, rh, rc, rhh);
+        bool any = false;
+        for (uint32_t p = 0; p < npg && !any; ++p) any = ((live >> p) & 1u) && box_reaches(w + 12 * p, rc, rhh, a);
+        return any;
+    };
+    while (skip_lo < depth && !run_reaches(skip_lo, min(skip_lo + kSpanSlices, depth) - 1)) skip_lo += kSpanSlices;
+    if (skip_lo >= depth) {
+        live = 0u;  // no run reaches an occupied cell: nothing of the tile can count
+        skip_lo = 0;
+        return;
+    }
+    int top = depth;  // runs from the top: [top - kSpanSlices, top)
+    while (top - kSpanSlices > skip_lo && !run_reaches(top - kSpanSlices, top - 1)) top -= kSpanSlices;
+    skip_hi = depth - top;
+}
+
 template <int PT>
 __device__ __forceinline__ uint32_t live_mask(const KArgs &a, const Tile &t, uint32_t bx) {
     const int tiles = a.tiles_x * a.tiles_y;
@@ -1053,29 +1083,8 @@ __global__ __launch_bounds__(256) void k_cull_items(const KArgs a, uint32_t tota
         const int depth = hi[2] - lo[2] + 1;
         const unsigned long long area = (unsigned long long)(hi[0] - lo[0] + 1) * (unsigned long long)(hi[1] - lo[1] + 1);
         covered = (unsigned long long)npg * area * depth;
-        // slices of the tile's bottom and top runs that no live particle reaches
         int skip_lo = 0, skip_hi = 0;
-        if (live && depth > kSpanSlices && depth <= kSpanMaxDepth) {
-            const auto run_reaches = [&](int r0, int r1) {
-                const int rl[3] = {lo[0], lo[1], lo[2] + r0}, rh[3] = {hi[0], hi[1], lo[2] + r1};
-                float rc[3], rhh[3];
-                box_centre(rl, rh, rc, rhh);
-                bool any = false;
-                for (uint32_t p = 0; p < npg && !any; ++p)
-                    any = ((live >> p) & 1u) && box_reaches(a.words + 12 * (size_t)(pbase + p), rc, rhh, a);
-                return any;
-            };
-            while (skip_lo < depth && !run_reaches(skip_lo, min(skip_lo + kSpanSlices, depth) - 1))
-                skip_lo += kSpanSlices;
-            if (skip_lo >= depth) {
-                live = 0u;  // no run reaches an occupied cell: nothing of the tile can count
-            } else {
-                skip_lo = min(skip_lo, depth - 1);
-                int top = depth;  // runs from the top: [top - kSpanSlices, top)
-                while (top - kSpanSlices > skip_lo && !run_reaches(top - kSpanSlices, top - 1)) top -= kSpanSlices;
-                skip_hi = depth - top;
-            }
-        }
+        trim_span(a, a.words + 12 * (size_t)pbase, npg, lo, hi, live, skip_lo, skip_hi);
         evaluated = (unsigned long long)__popc(live) * area * (unsigned long long)(depth - skip_lo - skip_hi);
         if (live && inside) {
             live |= 1u << kInteriorBit;
@@ -1213,8 +1222,8 @@ void k_batch_score(const BatchArgs b) {
 
 // Mask classes: the live items of an iteration.  One thread per entry of the
 // class's XCD lists tests its (tile, particle group) item against its pair's
-// source mask box and appends live items, with their particle masks and
-// interior bits, to the same list's part of `live` (one atomic per wave where
+// source mask box and appends live items, with their particle masks, interior
+// bits and slice spans, to the same list's part of `live` (one atomic per wave where
 // all its lanes are in one list); pairs past their last iteration add nothing.
 template <int PT>
 __global__ __launch_bounds__(256) void k_batch_cull(const BatchArgs b, uint2 *live, uint32_t *counts) {
@@ -1247,7 +1256,10 @@ __global__ __launch_bounds__(256) void k_batch_cull(const BatchArgs b, uint2 *li
                     lm |= 1u << p;
                     inside = inside && box_inside(a.words + 12 * (size_t)(pbase + p), c, h, a);
                 }
+            int skip_lo = 0, skip_hi = 0;
+            trim_span(a, a.words + 12 * (size_t)pbase, npg, lo, hi, lm, skip_lo, skip_hi);
             if (lm && inside) lm |= 1u << kInteriorBit;
+            if (lm) lm |= ((uint32_t)skip_lo << kSpanLoBit) | ((uint32_t)skip_hi << kSpanHiBit);
         }
     }
     const uint32_t lane = threadIdx.x % 64u;
