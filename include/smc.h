@@ -266,8 +266,9 @@ smc_status smc_profile_read(smc_ctx *ctx, double *score_ms, uint64_t *score_laun
 
 /* Work of the filter's culled mask launches (masks, Methods: the Dice
  * evaluation; image contexts report 0).  Tile culling skips a particle for a
- * target tile when no sample of the tile's image can read an "on" source
- * voxel: the image's box misses the source mask's bounding box or covers only
+ * target tile, and a tile's runs of four slices at its bottom and top for all
+ * its particles, when no sample there can read an "on" source voxel: the
+ * image's box misses the source mask's bounding box or covers only
  * unoccupied 2^3-voxel cells.  Returns, since the previous call (or
  * smc_init), the particle x voxel pairs those launches evaluated, the pairs
  * they covered (the skipped ones included) and, of the evaluated ones, those
